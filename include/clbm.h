@@ -1,0 +1,181 @@
+/*
+ * clbm.h -- C ABI of the MI355X (gfx950) D3Q27 cascaded lattice Boltzmann
+ * library: the collide-and-stream update of Fei, Luo & Li, "Three-dimensional
+ * cascaded lattice Boltzmann method: improved implementation and consistent
+ * forcing scheme" (arXiv:1801.04586), its adjoint, and reduced-precision
+ * population storage.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Lattice: nx * ny * nz nodes, node id n = x + nx * (y + ny * z), x fastest.
+ *    N = nx * ny * nz must be below 2^31.  Lattice units: dx = dt = 1,
+ *    c_s^2 = 1/3 (Sec. II A).
+ *  - Axes: wall[a] = 0 makes axis a periodic; wall[a] = 1 puts stationary
+ *    half-way bounce-back walls at both ends of axis a (Sec. III): a population
+ *    leaving fluid node x towards a wall or a solid node returns to x,
+ *    reversed, one step later.  On a walled axis node j sits at coordinate
+ *    j + 1/2 with walls at 0 and n.
+ *  - Populations i = 0..26 follow the velocity order of Eq. (1).
+ *  - Pointers are device pointers unless a comment says "host".  Every device
+ *    buffer is allocated and freed by the caller; the library never frees
+ *    caller memory.  Buffers must be 16-byte aligned.
+ *  - All work is enqueued on the context's stream (a hipStream_t passed as
+ *    void*, NULL = default stream) and is asynchronous, except where noted.
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ *  - Every function returns a clbm_status; argument errors are detected on the
+ *    host before any HIP call is made.  CLBM_EHIP carries the HIP error text in
+ *    clbm_last_error().
+ *
+ * State buffers
+ * -------------
+ * A state is one array [27][nz][ny][nx] of the storage type.  Its contents are
+ * the populations in "pull" order: entry [i][y] holds the pre-collision
+ * population f_i(y + e_i, t) when y + e_i is a fluid node, and f_opp(i)(y, t)
+ * (the one that bounces back into y) when the link from y along e_i is
+ * blocked by a wall or a solid node.  Equivalently it holds the post-collision
+ * populations f*_i(y, t-1) of Eq. (7) before the streaming of Eq. (8).
+ * clbm_get_populations/clbm_set_populations convert from/to plain
+ * pre-collision populations f(x, t).  Storage types:
+ *    CLBM_F64  stores f_i itself, arithmetic in FP64;
+ *    CLBM_F32, CLBM_F16, CLBM_BF16 store the deviation f_i - w_i from the
+ *    rest-state weights (8/27, 2/27, 1/54, 1/216), rounded to nearest even,
+ *    arithmetic in FP32.
+ * Entries belonging to solid nodes are never read or written by the step.
+ */
+#ifndef CLBM_H
+#define CLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CLBM_ABI_VERSION 1
+
+typedef enum clbm_dtype {
+    CLBM_F64 = 0,
+    CLBM_F32 = 1,
+    CLBM_F16 = 2,
+    CLBM_BF16 = 3
+} clbm_dtype;
+
+typedef enum clbm_status {
+    CLBM_OK = 0,
+    CLBM_EINVAL = 1,     /* bad dims, null/misaligned pointer, bad argument */
+    CLBM_ERATE = 2,      /* a relaxation rate outside (0, 2) */
+    CLBM_EDTYPE = 3,     /* unknown storage type */
+    CLBM_EHIP = 4,       /* a HIP runtime call or kernel launch failed */
+    CLBM_ENONFINITE = 5  /* clbm_moments found a non-finite value or rho <= 0 */
+} clbm_status;
+
+/* Static description of a lattice.  Rates and force can be changed later with
+ * clbm_set_rates / clbm_set_force. */
+typedef struct clbm_desc {
+    int32_t nx, ny, nz;       /* >= 1 each, nx * ny * nz < 2^31 */
+    int32_t wall[3];          /* per axis: 0 periodic, 1 half-way bounce-back walls */
+    int32_t storage;          /* clbm_dtype */
+    int32_t reserved;         /* must be 0 */
+    /* Relaxation rates of Eq. (13), in this order:
+     * s0, s1, s2 (= s_nu, shear: nu = (1/s2 - 1/2)/3), s2b (bulk:
+     * xi = 2/3 (1/s2b - 1/2)/3), s3, s3b, s4, s4b, s5, s6.  Each in (0, 2). */
+    double s[10];
+    /* Body force density F(x) = force_uniform + force_scale * force[.][x]
+     * (Eq. (6), (9), (16)).  force: device [3][N], FP64 for CLBM_F64 storage,
+     * FP32 otherwise, or NULL. */
+    double force_uniform[3];
+    double force_scale;
+    const void *force;
+    /* Solid mask: device uint8 [N], nonzero = solid, or NULL (all fluid). */
+    const uint8_t *solid;
+} clbm_desc;
+
+typedef struct clbm_ctx clbm_ctx;
+
+/* ABI version of the loaded library (CLBM_ABI_VERSION). */
+int clbm_abi_version(void);
+
+/* Static text for a status code.  Never NULL. */
+const char *clbm_strerror(int status);
+
+/* Text of the last error on this context (may include HIP's message).  Never NULL. */
+const char *clbm_last_error(const clbm_ctx *ctx);
+
+/* Create a context for the lattice *desc (copied; the force and solid buffers
+ * are referenced, not copied, and must outlive their use).  stream: hipStream_t
+ * or NULL.  Allocates only small device scratch for reductions (< 1 MiB).
+ * *out is set to NULL on error. */
+int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream);
+
+/* Release the context and its scratch (synchronises its stream). NULL is a no-op. */
+int clbm_destroy(clbm_ctx *ctx);
+
+/* Change the stream subsequent calls enqueue on. */
+int clbm_set_stream(clbm_ctx *ctx, void *stream);
+
+/* Replace the ten relaxation rates of Eq. (13) (host array, order as in clbm_desc). */
+int clbm_set_rates(clbm_ctx *ctx, const double *s);
+
+/* Replace the body force: uniform (host, 3 doubles, or NULL = 0), per-node field
+ * (device [3][N] as in clbm_desc, or NULL) and the scale applied to the field. */
+int clbm_set_force(clbm_ctx *ctx, const double *uniform, const void *field, double scale);
+
+/* Initial state: writes into `state` the populations f = f_eq(rho0, u0) of the
+ * generalized local equilibrium (NM)^-1 T_eq (Sec. II B, Eq. (15)).
+ * rho0: device FP64 [N] or NULL (rho = 1); u0: device FP64 [3][N] or NULL (u = 0). */
+int clbm_init(clbm_ctx *ctx, void *state, const double *rho0, const double *u0);
+
+/* One time step, Steps 1-4 of Sec. II B fused in one kernel: pull-stream with
+ * bounce-back (Eq. (8)), rho and u (Eq. (9)), raw moments (Eq. (4), (14)),
+ * central shift N(u), collision (Eq. (5), (13), (15), (16)), back-shift N^-1 and
+ * M^-1 (Eq. (7)).  src and dst are distinct state buffers. */
+int clbm_step(clbm_ctx *ctx, const void *src, void *dst);
+
+/* nsteps steps alternating between a and b, starting from the state in a.
+ * The result is in a when nsteps is even and in b when it is odd. */
+int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps);
+
+/* Copy a state buffer (checkpoints).  src and dst distinct. */
+int clbm_copy(clbm_ctx *ctx, const void *src, void *dst);
+
+/* Macroscopic fields of Eq. (9) from a state: rho device FP64 [N] or NULL,
+ * u device FP64 [3][N] or NULL (solid nodes get 0).  totals (host, 4 doubles)
+ * or NULL: FP64 sums over fluid nodes of rho and rho*u (deterministic
+ * two-pass reduction); n_bad (host) or NULL: number of fluid nodes with a
+ * non-finite rho/u or rho <= 0.  When totals or n_bad is non-NULL the call
+ * synchronises the stream and returns CLBM_ENONFINITE if n_bad > 0. */
+int clbm_moments(clbm_ctx *ctx, const void *state, double *rho, double *u, double *totals, int64_t *n_bad);
+
+/* Pre-collision populations f(x, t) of a state, as device FP64 [27][N] in
+ * Eq. (1) order (f itself, not the deviation).  Solid nodes get 0. */
+int clbm_get_populations(clbm_ctx *ctx, const void *state, double *f);
+
+/* Inverse of clbm_get_populations: writes into `state` the buffer whose
+ * pre-collision populations are f (device FP64 [27][N]); values are rounded to
+ * the storage type.  Solid-node entries are left untouched. */
+int clbm_set_populations(clbm_ctx *ctx, const double *f, void *state);
+
+/* Adjoint of one time step (the exact transpose of clbm_step's map; not in the
+ * paper).  state_t: the state buffer clbm_step read to go from t to t+1.
+ * lam_next: dJ/df(t+1), lam_out: dJ/df(t), both [27][N] of the adjoint type
+ * (FP64 for CLBM_F64 storage, FP32 otherwise), pre-collision populations in
+ * Eq. (1) order, distinct buffers; zero on solid nodes.
+ * dJdF: device [3][N] of the adjoint type or NULL; dJ/dF(x) of this step is
+ * added to it.  dJds: device FP64 [10] or NULL; dJ/ds_k of this step (summed
+ * over nodes in FP64, fixed order) is added to it. */
+int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, void *dJdF,
+                      double *dJds);
+
+/* Loss J = 1/2 sum over fluid nodes |u(x) - u_target(x)|^2 with u of Eq. (9)
+ * evaluated on `state`.  u_target: device [3][N] of the adjoint type.
+ * lam_out: dJ/df [27][N] (adjoint type), the seed of the adjoint recursion.
+ * dJdF (device [3][N] or NULL): the direct dependence of u on F/2 is added.
+ * J (device FP64 [1] or NULL): J is added to *J (FP64, fixed-order sum). */
+int clbm_loss_seed(clbm_ctx *ctx, const void *state, const void *u_target, void *lam_out, void *dJdF, double *J);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLBM_H */

@@ -58,18 +58,26 @@ static const double CS2 = 1.0 / 3.0; /* c_s^2, Sec. II A */
 static int e_of(int i, int axis) { return axis == 0 ? EX[i] : (axis == 1 ? EY[i] : EZ[i]); }
 static int p_of(int a, int axis) { return axis == 0 ? PX[a] : (axis == 1 ? PY[a] : PZ[a]); }
 
+/* x^n for the small exponents n = 0, 1, 2 (and 3 for derivatives) used here; x^0 = 1. */
 static double ipow(double x, int n)
 {
-    double r = 1.0;
-    for (int k = 0; k < n; ++k) r *= x;
-    return r;
+    switch (n) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return x * x;
+    default: {
+        double r = 1.0;
+        for (int k = 0; k < n; ++k) r *= x;
+        return r;
+    }
+    }
 }
 
+/* binomial coefficient C(n, k) for 0 <= k <= n <= 2 */
 static double binom(int n, int k)
 {
-    double r = 1.0;
-    for (int j = 1; j <= k; ++j) r = r * (double)(n - k + j) / (double)j;
-    return r;
+    static const double tab[3][3] = {{1, 0, 0}, {1, 1, 0}, {1, 2, 1}};
+    return tab[n][k];
 }
 
 /* opposite population: the index j with e_j = -e_i */
@@ -97,16 +105,6 @@ static void matTvec(const double *A, const double *x, double *y)
         for (int r = 0; r < Q; ++r) acc += A[r * Q + c] * x[r];
         y[c] = acc;
     }
-}
-
-static void matmul(const double *A, const double *B, double *C)
-{
-    for (int r = 0; r < Q; ++r)
-        for (int c = 0; c < Q; ++c) {
-            double acc = 0.0;
-            for (int k = 0; k < Q; ++k) acc += A[r * Q + k] * B[k * Q + c];
-            C[r * Q + c] = acc;
-        }
 }
 
 /* Gauss-Jordan elimination with partial pivoting; returns 0 on success. */
@@ -151,12 +149,12 @@ static int invert(int n, const double *A, double *Ainv)
  * With u = 0 this is the raw-moment matrix M of Eq. (14). */
 void orc_matrix_K(const double *u, double *K)
 {
+    double pw[Q][3][3]; /* pw[i][axis][p] = (e_i,axis - u_axis)^p */
+    for (int i = 0; i < Q; ++i)
+        for (int ax = 0; ax < 3; ++ax)
+            for (int p = 0; p < 3; ++p) pw[i][ax][p] = ipow((double)e_of(i, ax) - u[ax], p);
     for (int a = 0; a < Q; ++a)
-        for (int i = 0; i < Q; ++i) {
-            double v = 1.0;
-            for (int ax = 0; ax < 3; ++ax) v *= ipow((double)e_of(i, ax) - u[ax], p_of(a, ax));
-            K[a * Q + i] = v;
-        }
+        for (int i = 0; i < Q; ++i) K[a * Q + i] = pw[i][0][PX[a]] * pw[i][1][PY[a]] * pw[i][2][PZ[a]];
 }
 
 /* Eq. (4) + Eq. (14): M, the raw moments k_mnp = <f | e_x^m e_y^n e_z^p>. */

@@ -1,0 +1,304 @@
+"""ctypes binding of libclbm.so (include/clbm.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of the library; this module
+passes torch tensors' device pointers and the current HIP stream through the C
+ABI and turns status codes into exceptions.  There is no fallback: if the
+library is missing or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclbm.so")
+
+CLBM_F64, CLBM_F32, CLBM_F16, CLBM_BF16 = 0, 1, 2, 3
+STORAGE = {"f64": CLBM_F64, "f32": CLBM_F32, "f16": CLBM_F16, "bf16": CLBM_BF16}
+STORAGE_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+# arithmetic / adjoint / force-field type per storage
+REAL_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float32, "bf16": torch.float32}
+RATE_NAMES = ("s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6")
+
+
+class ClbmError(RuntimeError):
+    def __init__(self, func: str, code: int, msg: str):
+        super().__init__(f"{func} failed ({code}): {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("wall", ctypes.c_int32 * 3),
+        ("storage", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("s", ctypes.c_double * 10),
+        ("force_uniform", ctypes.c_double * 3),
+        ("force_scale", ctypes.c_double),
+        ("force", ctypes.c_void_p),
+        ("solid", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libclbm.so and declare its C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(path)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "clbm_abi_version": ([], ctypes.c_int),
+        "clbm_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "clbm_last_error": ([vp], ctypes.c_char_p),
+        "clbm_create": ([ctypes.POINTER(vp), ctypes.POINTER(Desc), vp], ctypes.c_int),
+        "clbm_destroy": ([vp], ctypes.c_int),
+        "clbm_set_stream": ([vp, vp], ctypes.c_int),
+        "clbm_set_rates": ([vp, dp], ctypes.c_int),
+        "clbm_set_force": ([vp, dp, vp, ctypes.c_double], ctypes.c_int),
+        "clbm_init": ([vp, vp, vp, vp], ctypes.c_int),
+        "clbm_step": ([vp, vp, vp], ctypes.c_int),
+        "clbm_run": ([vp, vp, vp, i32], ctypes.c_int),
+        "clbm_copy": ([vp, vp, vp], ctypes.c_int),
+        "clbm_moments": ([vp, vp, vp, vp, dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "clbm_get_populations": ([vp, vp, vp], ctypes.c_int),
+        "clbm_set_populations": ([vp, vp, vp], ctypes.c_int),
+        "clbm_adjoint_step": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "clbm_loss_seed": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    if L.clbm_abi_version() != 1:
+        raise ImportError("libclbm.so ABI version mismatch")
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return load_library().clbm_strerror(code).decode()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """Owns a clbm_ctx.  Method names follow the C ABI (clbm_<name>)."""
+
+    def __init__(self, desc: Desc, device: torch.device):
+        self.lib = load_library()
+        self.device = device
+        self._h = ctypes.c_void_p()
+        rc = self.lib.clbm_create(ctypes.byref(self._h), ctypes.byref(desc), _stream(device))
+        if rc:
+            raise ClbmError("clbm_create", rc, self.lib.clbm_last_error(None).decode())
+        self.desc = desc
+
+    def _call(self, name, *args):
+        fn = getattr(self.lib, name)
+        self.lib.clbm_set_stream(self._h, _stream(self.device))
+        rc = fn(self._h, *args)
+        if rc:
+            raise ClbmError(name, rc, self.lib.clbm_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if self._h:
+            self.lib.clbm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- ABI mirrors
+    def set_rates(self, s):
+        arr = (ctypes.c_double * 10)(*[float(v) for v in s])
+        self._call("clbm_set_rates", arr)
+
+    def set_force(self, uniform, field: Optional[torch.Tensor], scale: float):
+        u = (ctypes.c_double * 3)(*[float(v) for v in uniform])
+        self._call("clbm_set_force", u, _ptr(field), ctypes.c_double(float(scale)))
+
+    def init(self, state, rho0=None, u0=None):
+        self._call("clbm_init", _ptr(state), _ptr(rho0), _ptr(u0))
+
+    def step(self, src, dst):
+        self._call("clbm_step", _ptr(src), _ptr(dst))
+
+    def run(self, a, b, nsteps: int):
+        self._call("clbm_run", _ptr(a), _ptr(b), ctypes.c_int32(int(nsteps)))
+
+    def copy(self, src, dst):
+        self._call("clbm_copy", _ptr(src), _ptr(dst))
+
+    def moments(self, state, rho=None, u=None, want_totals=True):
+        totals = (ctypes.c_double * 4)() if want_totals else None
+        nbad = ctypes.c_int64(0) if want_totals else None
+        fn = self.lib.clbm_moments
+        self.lib.clbm_set_stream(self._h, _stream(self.device))
+        rc = fn(self._h, _ptr(state), _ptr(rho), _ptr(u), totals, ctypes.byref(nbad) if want_totals else None)
+        if rc and rc != 5:
+            raise ClbmError("clbm_moments", rc, self.lib.clbm_last_error(self._h).decode())
+        if not want_totals:
+            return None, None
+        return np.array(list(totals)), int(nbad.value)
+
+    def get_populations(self, state, out):
+        self._call("clbm_get_populations", _ptr(state), _ptr(out))
+
+    def set_populations(self, f, state):
+        self._call("clbm_set_populations", _ptr(f), _ptr(state))
+
+    def adjoint_step(self, state_t, lam_next, lam_out, dJdF=None, dJds=None):
+        self._call("clbm_adjoint_step", _ptr(state_t), _ptr(lam_next), _ptr(lam_out), _ptr(dJdF), _ptr(dJds))
+
+    def loss_seed(self, state, u_target, lam_out, dJdF=None, J=None):
+        self._call("clbm_loss_seed", _ptr(state), _ptr(u_target), _ptr(lam_out), _ptr(dJdF), _ptr(J))
+
+
+def make_desc(dims, walls=(0, 0, 0), storage="f32", rates=None, force=(0.0, 0.0, 0.0), force_field=None,
+              force_scale=1.0, solid=None) -> Desc:
+    d = Desc()
+    d.nx, d.ny, d.nz = (int(v) for v in dims)
+    for a in range(3):
+        d.wall[a] = int(walls[a])
+    d.storage = STORAGE[storage]
+    d.reserved = 0
+    rates = [1.0] * 10 if rates is None else [float(v) for v in rates]
+    for k in range(10):
+        d.s[k] = rates[k]
+    for a in range(3):
+        d.force_uniform[a] = float(force[a])
+    d.force_scale = float(force_scale)
+    d.force = None if force_field is None else force_field.data_ptr()
+    d.solid = None if solid is None else solid.data_ptr()
+    return d
+
+
+def _dev_tensor(a, dtype, device, shape=None) -> Optional[torch.Tensor]:
+    if a is None:
+        return None
+    t = torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a)
+    t = t.to(device=device, dtype=dtype).contiguous()
+    if shape is not None:
+        t = t.reshape(shape)
+    return t
+
+
+class Lattice:
+    """A D3Q27 cascaded-LBM lattice on one GPU: two state buffers and a context.
+
+    dims = (nx, ny, nz); walls per axis (0 periodic, 1 half-way bounce-back);
+    storage in {"f64", "f32", "f16", "bf16"}; rates = the 10 rates of Eq. (13);
+    force = uniform force density; force_field = (3, nz, ny, nx) field added to
+    it (times force_scale); solid = (nz, ny, nx) mask, nonzero = solid.
+    """
+
+    def __init__(self, dims: Sequence[int], walls=(0, 0, 0), storage="f32", rates=None, force=(0.0, 0.0, 0.0),
+                 force_field=None, force_scale=1.0, solid=None, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("clbm needs a GPU (HIP); none is visible")
+        self.device = torch.device(device if device is not None else "cuda")
+        self.dims = tuple(int(v) for v in dims)
+        nx, ny, nz = self.dims
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self.walls = tuple(int(w) for w in walls)
+        self.storage = storage
+        self.real = REAL_TORCH[storage]
+        self.force_field = _dev_tensor(force_field, self.real, self.device, (3,) + self.shape)
+        self.solid = _dev_tensor(solid, torch.uint8, self.device, self.shape)
+        self.rates = np.array([1.0] * 10 if rates is None else rates, dtype=np.float64)
+        self.force = tuple(float(v) for v in force)
+        self.force_scale = float(force_scale)
+        desc = make_desc(self.dims, self.walls, storage, self.rates, self.force, self.force_field, force_scale,
+                         self.solid)
+        self.ctx = Context(desc, self.device)
+        self.bufs = [torch.empty((27,) + self.shape, dtype=STORAGE_TORCH[storage], device=self.device)
+                     for _ in range(2)]
+        self.cur = 0
+        self.t = 0
+
+    # ---- state
+    @property
+    def state(self) -> torch.Tensor:
+        return self.bufs[self.cur]
+
+    @property
+    def other(self) -> torch.Tensor:
+        return self.bufs[1 - self.cur]
+
+    def init(self, rho0=None, u0=None):
+        r = _dev_tensor(rho0, torch.float64, self.device, self.shape)
+        u = _dev_tensor(u0, torch.float64, self.device, (3,) + self.shape)
+        self.ctx.init(self.state, r, u)
+        self.t = 0
+        return self
+
+    def step(self, n: int = 1):
+        n = int(n)
+        if n <= 0:
+            return self
+        self.ctx.run(self.state, self.other, n)
+        if n % 2:
+            self.cur = 1 - self.cur
+        self.t += n
+        return self
+
+    def set_rates(self, rates):
+        self.rates = np.asarray(rates, dtype=np.float64)
+        self.ctx.set_rates(self.rates)
+
+    def set_force(self, force=(0.0, 0.0, 0.0), force_field=None, force_scale=1.0):
+        self.force = tuple(float(v) for v in force)
+        self.force_field = _dev_tensor(force_field, self.real, self.device, (3,) + self.shape)
+        self.force_scale = float(force_scale)
+        self.ctx.set_force(self.force, self.force_field, self.force_scale)
+
+    # ---- observables
+    def moments(self, fields: bool = True):
+        """Returns (rho (nz,ny,nx) f64, u (3,nz,ny,nx) f64, totals [mass, px, py, pz], n_bad)."""
+        rho = torch.empty(self.shape, dtype=torch.float64, device=self.device) if fields else None
+        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device) if fields else None
+        totals, nbad = self.ctx.moments(self.state, rho, u, want_totals=True)
+        return rho, u, totals, nbad
+
+    def populations(self) -> torch.Tensor:
+        """Pre-collision populations f(x, t) as f64 (27, nz, ny, nx), Eq. (1) order."""
+        out = torch.empty((27,) + self.shape, dtype=torch.float64, device=self.device)
+        self.ctx.get_populations(self.state, out)
+        return out
+
+    def set_populations(self, f):
+        ft = _dev_tensor(f, torch.float64, self.device, (27,) + self.shape)
+        self.ctx.set_populations(ft, self.state)
+
+    def close(self):
+        self.ctx.close()

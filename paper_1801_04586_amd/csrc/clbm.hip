@@ -1,0 +1,430 @@
+// Host side of the C ABI declared in include/clbm.h: argument validation,
+// launch geometry, variant dispatch and FP64 reductions for the D3Q27 cascaded
+// LBM kernels in kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/clbm.h"
+#include "kernels.hpp"
+
+using namespace clbm;
+
+namespace {
+
+constexpr int kMaxBlocks = 2048;   // grid of the grid-stride kernels (8 blocks per CU)
+constexpr int kPartialStride = 8;  // doubles per block in the partials buffer (>= kMomComp, kAdjRates)
+
+thread_local char g_err[512] = "no error";
+
+}  // namespace
+
+struct clbm_ctx {
+    clbm_desc d;
+    hipStream_t stream;
+    Geom geom;
+    size_t nodes;
+    double *partials;  // [kMaxBlocks][kPartialStride]
+    double *scal;      // [16] reduction results
+    char err[512];
+};
+
+namespace {
+
+int fail(clbm_ctx *c, int code, const char *fmt, const char *arg = "")
+{
+    char *dst = c ? c->err : g_err;
+    std::snprintf(dst, 512, fmt, arg);
+    return code;
+}
+
+int hip_fail(clbm_ctx *c, hipError_t e, const char *what)
+{
+    char *dst = c ? c->err : g_err;
+    std::snprintf(dst, 512, "%s: %s", what, hipGetErrorString(e));
+    return CLBM_EHIP;
+}
+
+int check_launch(clbm_ctx *c, const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CLBM_OK : hip_fail(c, e, what);
+}
+
+bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int validate_rates(clbm_ctx *c, const double *s)
+{
+    static const char *const names[10] = {"s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6"};
+    for (int k = 0; k < 10; ++k)
+        if (!(s[k] > 0.0 && s[k] < 2.0)) return fail(c, CLBM_ERATE, "relaxation rate %s outside (0, 2)", names[k]);
+    return CLBM_OK;
+}
+
+int validate_desc(const clbm_desc *d)
+{
+    if (!d) return fail(nullptr, CLBM_EINVAL, "desc is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(nullptr, CLBM_EINVAL, "lattice dims must be >= 1");
+    const long long n = static_cast<long long>(d->nx) * d->ny * d->nz;
+    if (n >= (1ll << 31)) return fail(nullptr, CLBM_EINVAL, "nx*ny*nz must be below 2^31");
+    for (int a = 0; a < 3; ++a)
+        if (d->wall[a] != 0 && d->wall[a] != 1) return fail(nullptr, CLBM_EINVAL, "wall flags must be 0 or 1");
+    if (d->storage < CLBM_F64 || d->storage > CLBM_BF16) return fail(nullptr, CLBM_EDTYPE, "unknown storage type");
+    if (d->reserved != 0) return fail(nullptr, CLBM_EINVAL, "reserved field must be 0");
+    int rc = validate_rates(nullptr, d->s);
+    if (rc) return rc;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d->force_uniform[a])) return fail(nullptr, CLBM_EINVAL, "force_uniform not finite");
+    if (!std::isfinite(d->force_scale)) return fail(nullptr, CLBM_EINVAL, "force_scale not finite");
+    if (d->force && !aligned(d->force)) return fail(nullptr, CLBM_EINVAL, "force field not 16-byte aligned");
+    return CLBM_OK;
+}
+
+size_t store_size(int storage) { return storage == CLBM_F64 ? 8 : (storage == CLBM_F32 ? 4 : 2); }
+
+template <typename R>
+Rates<R> make_rates(const double *s)
+{
+    Rates<R> r;
+    for (int k = 0; k < 10; ++k) {
+        r.s[k] = static_cast<R>(s[k]);
+        r.hs[k] = static_cast<R>(1.0 - 0.5 * s[k]);
+    }
+    r.sm = static_cast<R>((s[R_S2B] - s[R_S2]) / 3.0);
+    return r;
+}
+
+template <typename R>
+Forcing<R> make_forcing(const clbm_desc &d)
+{
+    Forcing<R> f;
+    for (int a = 0; a < 3; ++a) f.F[a] = static_cast<R>(d.force_uniform[a]);
+    f.scale = static_cast<R>(d.force_scale);
+    return f;
+}
+
+// Compile-time variant of the kernels: storage type and which boundary/force code is needed.
+template <typename S, bool C, bool So, bool Fi>
+struct V {
+    using Store = S;
+    using R = typename Traits<S>::R;
+    static constexpr bool check = C, solid = So, field = Fi;
+};
+
+template <typename S, typename F>
+int dispatch_flags(const clbm_ctx *c, F &&f)
+{
+    const bool solid = c->d.solid != nullptr;
+    const bool check = solid || c->d.wall[0] || c->d.wall[1] || c->d.wall[2];
+    const bool field = c->d.force != nullptr;
+    if (solid) return field ? f(V<S, true, true, true>{}) : f(V<S, true, true, false>{});
+    if (check) return field ? f(V<S, true, false, true>{}) : f(V<S, true, false, false>{});
+    return field ? f(V<S, false, false, true>{}) : f(V<S, false, false, false>{});
+}
+
+template <typename F>
+int dispatch(const clbm_ctx *c, F &&f)
+{
+    switch (c->d.storage) {
+    case CLBM_F64: return dispatch_flags<double>(c, f);
+    case CLBM_F32: return dispatch_flags<float>(c, f);
+    case CLBM_F16: return dispatch_flags<_Float16>(c, f);
+    default: return dispatch_flags<__bf16>(c, f);
+    }
+}
+
+unsigned node_blocks(const clbm_ctx *c) { return static_cast<unsigned>((c->nodes + kBlock - 1) / kBlock); }
+unsigned stride_blocks(const clbm_ctx *c)
+{
+    const unsigned b = node_blocks(c);
+    return b < static_cast<unsigned>(kMaxBlocks) ? b : static_cast<unsigned>(kMaxBlocks);
+}
+
+int launch_step(clbm_ctx *c, const void *src, void *dst)
+{
+    return dispatch(c, [&](auto v) {
+        using Vt = decltype(v);
+        using S = typename Vt::Store;
+        using R = typename Vt::R;
+        hipLaunchKernelGGL((k_step<S, Vt::check, Vt::solid, Vt::field>), dim3(node_blocks(c)), dim3(kBlock), 0,
+                           c->stream, static_cast<const S *>(src), static_cast<S *>(dst), c->geom, c->d.solid,
+                           static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
+        return check_launch(c, "step kernel launch");
+    });
+}
+
+}  // namespace
+
+extern "C" {
+
+int clbm_abi_version(void) { return CLBM_ABI_VERSION; }
+
+const char *clbm_strerror(int status)
+{
+    switch (status) {
+    case CLBM_OK: return "success";
+    case CLBM_EINVAL: return "invalid argument";
+    case CLBM_ERATE: return "relaxation rate outside (0, 2)";
+    case CLBM_EDTYPE: return "unknown storage type";
+    case CLBM_EHIP: return "HIP runtime error";
+    case CLBM_ENONFINITE: return "non-finite or non-positive density/velocity found";
+    default: return "unknown status";
+    }
+}
+
+const char *clbm_last_error(const clbm_ctx *ctx) { return ctx ? ctx->err : g_err; }
+
+int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
+{
+    if (!out) return fail(nullptr, CLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+    clbm_ctx *c = new (std::nothrow) clbm_ctx();
+    if (!c) return fail(nullptr, CLBM_EINVAL, "out of host memory");
+    c->d = *desc;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->nodes = static_cast<size_t>(desc->nx) * desc->ny * desc->nz;
+    Geom &g = c->geom;
+    g.nx = desc->nx;
+    g.ny = desc->ny;
+    g.nz = desc->nz;
+    g.nxy = g.nx * g.ny;
+    g.N = static_cast<uint32_t>(c->nodes);
+    g.dnx.init(g.nx);
+    g.dny.init(g.ny);
+    for (int a = 0; a < 3; ++a) g.wall[a] = desc->wall[a];
+    std::snprintf(c->err, sizeof(c->err), "no error");
+    hipError_t e = hipMalloc(&c->partials, sizeof(double) * kMaxBlocks * kPartialStride);
+    if (e != hipSuccess) {
+        rc = hip_fail(nullptr, e, "hipMalloc(partials)");
+        delete c;
+        return rc;
+    }
+    e = hipMalloc(&c->scal, sizeof(double) * 16);
+    if (e != hipSuccess) {
+        rc = hip_fail(nullptr, e, "hipMalloc(scalars)");
+        (void)hipFree(c->partials);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return CLBM_OK;
+}
+
+int clbm_destroy(clbm_ctx *ctx)
+{
+    if (!ctx) return CLBM_OK;
+    int rc = CLBM_OK;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) rc = hip_fail(nullptr, e, "hipStreamSynchronize");
+    (void)hipFree(ctx->partials);
+    (void)hipFree(ctx->scal);
+    delete ctx;
+    return rc;
+}
+
+int clbm_set_stream(clbm_ctx *ctx, void *stream)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return CLBM_OK;
+}
+
+int clbm_set_rates(clbm_ctx *ctx, const double *s)
+{
+    if (!ctx || !s) return fail(ctx, CLBM_EINVAL, "ctx or rates is NULL");
+    int rc = validate_rates(ctx, s);
+    if (rc) return rc;
+    std::memcpy(ctx->d.s, s, sizeof(double) * 10);
+    return CLBM_OK;
+}
+
+int clbm_set_force(clbm_ctx *ctx, const double *uniform, const void *field, double scale)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (field && !aligned(field)) return fail(ctx, CLBM_EINVAL, "force field not 16-byte aligned");
+    if (!std::isfinite(scale)) return fail(ctx, CLBM_EINVAL, "force scale not finite");
+    double u[3] = {0.0, 0.0, 0.0};
+    if (uniform)
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(uniform[a])) return fail(ctx, CLBM_EINVAL, "uniform force not finite");
+            u[a] = uniform[a];
+        }
+    std::memcpy(ctx->d.force_uniform, u, sizeof(u));
+    ctx->d.force = field;
+    ctx->d.force_scale = scale;
+    return CLBM_OK;
+}
+
+int clbm_init(clbm_ctx *ctx, void *state, const double *rho0, const double *u0)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!state || !aligned(state)) return fail(ctx, CLBM_EINVAL, "state NULL or not 16-byte aligned");
+    if ((rho0 && !aligned(rho0)) || (u0 && !aligned(u0))) return fail(ctx, CLBM_EINVAL, "rho0/u0 not aligned");
+    return dispatch(ctx, [&](auto v) {
+        using Vt = decltype(v);
+        using S = typename Vt::Store;
+        hipLaunchKernelGGL((k_init<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0, ctx->stream,
+                           static_cast<S *>(state), ctx->geom, ctx->d.solid, rho0, u0);
+        return check_launch(ctx, "init kernel launch");
+    });
+}
+
+int clbm_step(clbm_ctx *ctx, const void *src, void *dst)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!src || !dst || !aligned(src) || !aligned(dst)) return fail(ctx, CLBM_EINVAL, "state NULL or misaligned");
+    if (src == dst) return fail(ctx, CLBM_EINVAL, "src and dst must be distinct");
+    return launch_step(ctx, src, dst);
+}
+
+int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!a || !b || !aligned(a) || !aligned(b) || a == b) return fail(ctx, CLBM_EINVAL, "bad state buffers");
+    if (nsteps < 0) return fail(ctx, CLBM_EINVAL, "nsteps < 0");
+    for (int32_t k = 0; k < nsteps; ++k) {
+        const int rc = (k & 1) ? launch_step(ctx, b, a) : launch_step(ctx, a, b);
+        if (rc) return rc;
+    }
+    return CLBM_OK;
+}
+
+int clbm_copy(clbm_ctx *ctx, const void *src, void *dst)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!src || !dst || !aligned(src) || !aligned(dst) || src == dst)
+        return fail(ctx, CLBM_EINVAL, "bad copy buffers");
+    const size_t bytes = ctx->nodes * 27 * store_size(ctx->d.storage);
+    const size_t n16 = bytes / 16, tail = bytes % 16;
+    if (n16) {
+        size_t blocks = (n16 + kBlock - 1) / kBlock;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(k_copy16, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, ctx->stream,
+                           static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+        int rc = check_launch(ctx, "copy kernel launch");
+        if (rc) return rc;
+    }
+    if (tail) {
+        hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, ctx->stream,
+                           static_cast<const uint8_t *>(src) + 16 * n16, static_cast<uint8_t *>(dst) + 16 * n16, tail);
+        return check_launch(ctx, "copy tail launch");
+    }
+    return CLBM_OK;
+}
+
+int clbm_moments(clbm_ctx *ctx, const void *state, double *rho, double *u, double *totals, int64_t *n_bad)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!state || !aligned(state)) return fail(ctx, CLBM_EINVAL, "state NULL or misaligned");
+    if ((rho && !aligned(rho)) || (u && !aligned(u))) return fail(ctx, CLBM_EINVAL, "rho/u not aligned");
+    const unsigned nb = stride_blocks(ctx);
+    int rc = dispatch(ctx, [&](auto v) {
+        using Vt = decltype(v);
+        using S = typename Vt::Store;
+        using R = typename Vt::R;
+        hipLaunchKernelGGL((k_moments<S, Vt::check, Vt::solid, Vt::field>), dim3(nb), dim3(kBlock), 0, ctx->stream,
+                           static_cast<const S *>(state), ctx->geom, ctx->d.solid, static_cast<const R *>(ctx->d.force),
+                           make_forcing<R>(ctx->d), rho, u, ctx->partials);
+        return check_launch(ctx, "moments kernel launch");
+    });
+    if (rc) return rc;
+    if (!totals && !n_bad) return CLBM_OK;
+    // partials use a stride of kMomComp per block: reduce with that stride
+    hipLaunchKernelGGL(k_reduce, dim3(kMomComp), dim3(kBlock), 0, ctx->stream, ctx->partials, static_cast<int>(nb),
+                       kMomComp, ctx->scal, 0);
+    rc = check_launch(ctx, "reduce kernel launch");
+    if (rc) return rc;
+    double h[kMomComp];
+    hipError_t e = hipMemcpyAsync(h, ctx->scal, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync(totals)");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    if (totals)
+        for (int k = 0; k < 4; ++k) totals[k] = h[k];
+    const int64_t bad = static_cast<int64_t>(h[4]);
+    if (n_bad) *n_bad = bad;
+    if (bad > 0) return fail(ctx, CLBM_ENONFINITE, "non-finite or non-positive density/velocity found");
+    return CLBM_OK;
+}
+
+int clbm_get_populations(clbm_ctx *ctx, const void *state, double *f)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!state || !f || !aligned(state) || !aligned(f)) return fail(ctx, CLBM_EINVAL, "bad buffers");
+    return dispatch(ctx, [&](auto v) {
+        using Vt = decltype(v);
+        using S = typename Vt::Store;
+        hipLaunchKernelGGL((k_get_populations<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
+                           ctx->stream, static_cast<const S *>(state), ctx->geom, ctx->d.solid, f);
+        return check_launch(ctx, "get_populations kernel launch");
+    });
+}
+
+int clbm_set_populations(clbm_ctx *ctx, const double *f, void *state)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!state || !f || !aligned(state) || !aligned(f)) return fail(ctx, CLBM_EINVAL, "bad buffers");
+    return dispatch(ctx, [&](auto v) {
+        using Vt = decltype(v);
+        using S = typename Vt::Store;
+        hipLaunchKernelGGL((k_set_populations<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
+                           ctx->stream, f, ctx->geom, ctx->d.solid, static_cast<S *>(state));
+        return check_launch(ctx, "set_populations kernel launch");
+    });
+}
+
+int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, void *dJdF,
+                      double *dJds)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!state_t || !lam_next || !lam_out || !aligned(state_t) || !aligned(lam_next) || !aligned(lam_out))
+        return fail(ctx, CLBM_EINVAL, "bad adjoint buffers");
+    if (lam_next == lam_out) return fail(ctx, CLBM_EINVAL, "lam_next and lam_out must be distinct");
+    if ((dJdF && !aligned(dJdF)) || (dJds && !aligned(dJds))) return fail(ctx, CLBM_EINVAL, "dJdF/dJds misaligned");
+    const unsigned nb = stride_blocks(ctx);
+    int rc = dispatch(ctx, [&](auto v) {
+        using Vt = decltype(v);
+        using S = typename Vt::Store;
+        using R = typename Vt::R;
+        hipLaunchKernelGGL((k_adjoint<S, Vt::check, Vt::solid, Vt::field>), dim3(nb), dim3(kBlock), 0, ctx->stream,
+                           static_cast<const S *>(state_t), ctx->geom, ctx->d.solid,
+                           static_cast<const R *>(ctx->d.force), make_forcing<R>(ctx->d), make_rates<R>(ctx->d.s),
+                           static_cast<const R *>(lam_next), static_cast<R *>(lam_out), static_cast<R *>(dJdF),
+                           ctx->partials);
+        return check_launch(ctx, "adjoint kernel launch");
+    });
+    if (rc || !dJds) return rc;
+    hipLaunchKernelGGL(k_reduce, dim3(kAdjRates), dim3(kBlock), 0, ctx->stream, ctx->partials, static_cast<int>(nb),
+                       kAdjRates, dJds + 2, 1);
+    return check_launch(ctx, "reduce kernel launch");
+}
+
+int clbm_loss_seed(clbm_ctx *ctx, const void *state, const void *u_target, void *lam_out, void *dJdF, double *J)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!state || !u_target || !lam_out || !aligned(state) || !aligned(u_target) || !aligned(lam_out))
+        return fail(ctx, CLBM_EINVAL, "bad loss buffers");
+    if ((dJdF && !aligned(dJdF)) || (J && (reinterpret_cast<uintptr_t>(J) & 7u)))
+        return fail(ctx, CLBM_EINVAL, "dJdF/J misaligned");
+    const unsigned nb = stride_blocks(ctx);
+    int rc = dispatch(ctx, [&](auto v) {
+        using Vt = decltype(v);
+        using S = typename Vt::Store;
+        using R = typename Vt::R;
+        hipLaunchKernelGGL((k_loss<S, Vt::check, Vt::solid, Vt::field>), dim3(nb), dim3(kBlock), 0, ctx->stream,
+                           static_cast<const S *>(state), ctx->geom, ctx->d.solid, static_cast<const R *>(ctx->d.force),
+                           make_forcing<R>(ctx->d), static_cast<const R *>(u_target), static_cast<R *>(lam_out),
+                           static_cast<R *>(dJdF), ctx->partials);
+        return check_launch(ctx, "loss kernel launch");
+    });
+    if (rc || !J) return rc;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, ctx->stream, ctx->partials, static_cast<int>(nb), 1, J, 1);
+    return check_launch(ctx, "reduce kernel launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,618 @@
+// HIP kernels of the D3Q27 cascaded LBM for gfx950 (MI355X).
+//
+// Memory layout: a state is [27][N] in the storage type (structure of arrays,
+// x fastest), so a wavefront of 64 lanes on 64 consecutive nodes reads and
+// writes 64 consecutive elements of each population plane.  The step is a
+// "pull" step: node x gathers population i from x - e_i of the previous
+// post-collision state (Eq. (8) read backwards), collides in registers and
+// writes its 27 post-collision values at x, so every store is aligned and
+// coalesced and every value crosses HBM exactly once in each direction.
+// Half-way bounce-back replaces a blocked pull by the node's own opposite
+// population.  The work per node is ~550 flops against 2 x 27 values moved, so
+// the kernel is bound by HBM bandwidth; nothing here is a dense contraction
+// and no MFMA is used.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "node.hpp"
+
+namespace clbm {
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------ storage types
+template <typename S>
+struct Traits;
+template <>
+struct Traits<double> {
+    using R = double;                   // arithmetic type
+    static constexpr bool kDev = false; // stores f itself
+};
+template <>
+struct Traits<float> {
+    using R = float;
+    static constexpr bool kDev = true;  // stores f - w
+};
+template <>
+struct Traits<_Float16> {
+    using R = float;
+    static constexpr bool kDev = true;
+};
+template <>
+struct Traits<__bf16> {
+    using R = float;
+    static constexpr bool kDev = true;
+};
+
+template <typename S>
+__device__ __forceinline__ typename Traits<S>::R to_real(S v) { return static_cast<typename Traits<S>::R>(v); }
+
+// Round a real (FP32 or FP64) to the storage type, nearest-even.
+template <typename S, typename R>
+__device__ __forceinline__ S to_store(R v)
+{
+    if constexpr (std::is_same<S, double>::value)
+        return static_cast<double>(v);
+    else
+        return static_cast<S>(static_cast<float>(v));
+}
+
+// ------------------------------------------------------------------ geometry
+// n / d for n < 2^31 by multiply-shift (Granlund-Montgomery with 31-bit
+// numerators): m = floor(2^(31+l) / d) + 1, l = ceil(log2 d).
+struct FastDiv {
+    uint64_t mul;
+    uint32_t shift;
+    uint32_t d;
+    __host__ void init(uint32_t d_)
+    {
+        d = d_;
+        uint32_t l = 0;
+        while ((1ull << l) < d_) ++l;
+        shift = 31 + l;
+        mul = ((1ull << shift) / d_) + 1;
+    }
+    __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const
+    {
+        return static_cast<uint32_t>((static_cast<uint64_t>(n) * mul) >> shift);
+    }
+};
+
+struct Geom {
+    uint32_t N, nx, ny, nz, nxy;
+    FastDiv dnx, dny;
+    int32_t wall[3];
+};
+
+// Pull sources of one node.  Index a = e + 1 per axis: xs[a] is the x of the node
+// x - e (wrapped on periodic axes), ys/zs the row/plane offsets; v* says whether
+// that neighbour exists (false beyond a wall).  Offsets stay in range even when
+// the neighbour does not exist.
+struct Nbr {
+    uint32_t xs[3], ys[3], zs[3];
+    bool vx[3], vy[3], vz[3];
+};
+
+__device__ __forceinline__ void axis_sources(uint32_t c, uint32_t n, int32_t wall, uint32_t (&s)[3], bool (&v)[3])
+{
+    // a = 0 (e = -1): source c + 1;  a = 1: c;  a = 2 (e = +1): source c - 1
+    const bool top = (c + 1 == n), bot = (c == 0);
+    s[0] = top ? 0u : c + 1;
+    s[1] = c;
+    s[2] = bot ? n - 1 : c - 1;
+    v[0] = !(top && wall);
+    v[1] = true;
+    v[2] = !(bot && wall);
+}
+
+__device__ __forceinline__ void node_coords(const Geom &g, uint32_t n, uint32_t &x, uint32_t &y, uint32_t &z)
+{
+    const uint32_t yz = g.dnx.div(n);
+    x = n - yz * g.nx;
+    z = g.dny.div(yz);
+    y = yz - z * g.ny;
+}
+
+__device__ __forceinline__ void neighbours(const Geom &g, uint32_t n, Nbr &nb)
+{
+    uint32_t x, y, z;
+    node_coords(g, n, x, y, z);
+    axis_sources(x, g.nx, g.wall[0], nb.xs, nb.vx);
+    axis_sources(y, g.ny, g.wall[1], nb.ys, nb.vy);
+    axis_sources(z, g.nz, g.wall[2], nb.zs, nb.vz);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        nb.ys[k] *= g.nx;
+        nb.zs[k] *= g.nxy;
+    }
+}
+
+// Is the link pulled by slot t open (neighbour x - e exists and is fluid)?  When
+// REV, the link towards x + e instead.
+template <int T, bool REV, bool SOLID>
+__device__ __forceinline__ bool link_open(const Nbr &nb, const uint8_t *__restrict__ solid, uint32_t &off)
+{
+    constexpr int a = REV ? 2 - sa(T) : sa(T), b = REV ? 2 - sb(T) : sb(T), c = REV ? 2 - sc(T) : sc(T);
+    off = nb.zs[c] + nb.ys[b] + nb.xs[a];
+    bool ok = nb.vx[a] && nb.vy[b] && nb.vz[c];
+    if constexpr (SOLID) ok = ok && (solid[off] == 0);
+    return ok;
+}
+
+// Gather of Eq. (8): v[t] = population of slot t arriving at node n, as a real
+// (the stored value, deviation or not).  REV gathers along +e instead (adjoint).
+template <typename S, bool CHECK, bool SOLID, bool REV, typename R>
+__device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
+                                       const uint8_t *__restrict__ solid, R (&v)[27])
+{
+    sfor<0, 27>([&](auto TT) {
+        constexpr int t = decltype(TT)::value;
+        constexpr int i = pop_of_slot(t);
+        const S *__restrict__ Pi = buf + static_cast<size_t>(i) * N;
+        if constexpr (t == 13) {
+            v[t] = static_cast<R>(to_real(Pi[n]));
+        } else {
+            uint32_t off;
+            const bool ok = link_open<t, REV, SOLID>(nb, solid, off);
+            if constexpr (CHECK) {
+                constexpr int ib = pop_of_slot(26 - t);
+                const S *p = ok ? (Pi + off) : (buf + static_cast<size_t>(ib) * N + n);
+                v[t] = static_cast<R>(to_real(*p));
+            } else {
+                v[t] = static_cast<R>(to_real(Pi[off]));
+            }
+        }
+    });
+}
+
+// Inverse of gather: write the value of slot t of node n where gather() reads it.
+template <typename S, bool CHECK, bool SOLID, typename R>
+__device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
+                                        const uint8_t *__restrict__ solid, const R (&v)[27])
+{
+    sfor<0, 27>([&](auto TT) {
+        constexpr int t = decltype(TT)::value;
+        constexpr int i = pop_of_slot(t);
+        S *__restrict__ Pi = buf + static_cast<size_t>(i) * N;
+        const S val = to_store<S>(v[t]);
+        if constexpr (t == 13) {
+            Pi[n] = val;
+        } else {
+            uint32_t off;
+            const bool ok = link_open<t, false, SOLID>(nb, solid, off);
+            if constexpr (CHECK) {
+                constexpr int ib = pop_of_slot(26 - t);
+                S *p = ok ? (Pi + off) : (buf + static_cast<size_t>(ib) * N + n);
+                *p = val;
+            } else {
+                Pi[off] = val;
+            }
+        }
+    });
+}
+
+template <typename R>
+struct Forcing {
+    R F[3];   // uniform part
+    R scale;  // multiplies the per-node field
+};
+
+template <bool FIELD, typename R>
+__device__ __forceinline__ void force_at(const Forcing<R> &fo, const R *__restrict__ field, uint32_t N, uint32_t n,
+                                         R &Fx, R &Fy, R &Fz)
+{
+    Fx = fo.F[0];
+    Fy = fo.F[1];
+    Fz = fo.F[2];
+    if constexpr (FIELD) {
+        Fx = fma(fo.scale, field[n], Fx);
+        Fy = fma(fo.scale, field[N + n], Fy);
+        Fz = fma(fo.scale, field[2 * static_cast<size_t>(N) + n], Fz);
+    }
+}
+
+// ------------------------------------------------------------------ forward step
+// One fused time step on one node per thread (Steps 1-4 of Sec. II B).
+template <typename S, bool CHECK, bool SOLID, bool FIELD>
+__global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *__restrict__ dst, Geom g,
+                                                 const uint8_t *__restrict__ solid,
+                                                 const typename Traits<S>::R *__restrict__ field,
+                                                 Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
+{
+    using R = typename Traits<S>::R;
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    if constexpr (SOLID)
+        if (solid[n]) return;
+    Nbr nb;
+    neighbours(g, n, nb);
+    R v[27];
+    gather<S, CHECK, SOLID, false>(src, g.N, n, nb, solid, v);
+    if constexpr (!Traits<S>::kDev)
+        sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+
+    raw_moments(v);  // Eq. (4), (14): T = M d
+    const R drho = v[slot(0, 0, 0)];
+    R Fx, Fy, Fz;
+    force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+    const R inv_rho = R(1) / (R(1) + drho);  // Eq. (9)
+    const R ux = (v[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho;
+    const R uy = (v[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho;
+    const R uz = (v[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho;
+    central_shift(v, ux, uy, uz);  // T~ = N(u) T
+    const AxisU<R> X(ux), Y(uy), Z(uz);
+    collide(v, drho, X, Y, Z, Fx, Fy, Fz, rt);  // Eq. (5)
+    reconstruct(v, ux, uy, uz);                 // Eq. (7): N^-1 then M^-1
+
+    sfor<0, 27>([&](auto TT) {
+        constexpr int t = decltype(TT)::value;
+        R val = v[t];
+        if constexpr (!Traits<S>::kDev) val += weight_of_slot<R>(t);
+        dst[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = to_store<S>(val);
+    });
+}
+
+// ------------------------------------------------------------------ block reductions (FP64, fixed order)
+template <int NC>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NC], double *__restrict__ out)
+{
+    __shared__ double red[kBlock / 64][NC];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double x = acc[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) red[wv][c] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Sum partials[b * stride + c] over b < nblocks for c = blockIdx.x; out[c] = (acc ? out[c] : 0) + sum.
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ partials, int nblocks, int stride,
+                                                   double *__restrict__ out, int accumulate)
+{
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[static_cast<size_t>(b) * stride + c];
+    double acc[1] = {s};
+    __shared__ double res[1];
+    block_reduce_store<1>(acc, res);
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = (accumulate ? out[c] : 0.0) + res[0];
+}
+
+// ------------------------------------------------------------------ macroscopic fields (Eq. (9))
+constexpr int kMomComp = 5;  // mass, momentum x/y/z, count of bad nodes
+
+template <typename S, bool CHECK, bool SOLID, bool FIELD>
+__global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, Geom g,
+                                                    const uint8_t *__restrict__ solid,
+                                                    const typename Traits<S>::R *__restrict__ field,
+                                                    Forcing<typename Traits<S>::R> fo, double *__restrict__ rho_out,
+                                                    double *__restrict__ u_out, double *__restrict__ partials)
+{
+    using R = typename Traits<S>::R;
+    double acc[kMomComp] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.N; n += gridDim.x * kBlock) {
+        if (SOLID && solid[n]) {
+            if (rho_out) rho_out[n] = 0.0;
+            if (u_out) u_out[n] = u_out[g.N + n] = u_out[2 * static_cast<size_t>(g.N) + n] = 0.0;
+            continue;
+        }
+        Nbr nb;
+        neighbours(g, n, nb);
+        double v[27];
+        gather<S, CHECK, SOLID, false>(src, g.N, n, nb, solid, v);
+        if constexpr (!Traits<S>::kDev)
+            sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<double>(decltype(T)::value); });
+        raw_moments(v);
+        R Fx, Fy, Fz;
+        force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+        const double rho = 1.0 + v[slot(0, 0, 0)];
+        const double mx = v[slot(1, 0, 0)] + 0.5 * static_cast<double>(Fx);
+        const double my = v[slot(0, 1, 0)] + 0.5 * static_cast<double>(Fy);
+        const double mz = v[slot(0, 0, 1)] + 0.5 * static_cast<double>(Fz);
+        const double ux = mx / rho, uy = my / rho, uz = mz / rho;
+        const bool bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz);
+        if (rho_out) rho_out[n] = rho;
+        if (u_out) {
+            u_out[n] = ux;
+            u_out[g.N + n] = uy;
+            u_out[2 * static_cast<size_t>(g.N) + n] = uz;
+        }
+        acc[0] += rho;
+        acc[1] += mx;
+        acc[2] += my;
+        acc[3] += mz;
+        acc[4] += bad ? 1.0 : 0.0;
+    }
+    block_reduce_store<kMomComp>(acc, partials + static_cast<size_t>(blockIdx.x) * kMomComp);
+}
+
+// ------------------------------------------------------------------ populations in/out, initial state
+template <typename S, bool CHECK, bool SOLID>
+__global__ __launch_bounds__(kBlock) void k_get_populations(const S *__restrict__ src, Geom g,
+                                                            const uint8_t *__restrict__ solid,
+                                                            double *__restrict__ f)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    if (SOLID && solid[n]) {
+        for (int i = 0; i < 27; ++i) f[static_cast<size_t>(i) * g.N + n] = 0.0;
+        return;
+    }
+    Nbr nb;
+    neighbours(g, n, nb);
+    double v[27];
+    gather<S, CHECK, SOLID, false>(src, g.N, n, nb, solid, v);
+    sfor<0, 27>([&](auto TT) {
+        constexpr int t = decltype(TT)::value;
+        double val = v[t];
+        if constexpr (Traits<S>::kDev) val += weight_of_slot<double>(t);
+        f[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = val;
+    });
+}
+
+template <typename S, bool CHECK, bool SOLID>
+__global__ __launch_bounds__(kBlock) void k_set_populations(const double *__restrict__ f, Geom g,
+                                                            const uint8_t *__restrict__ solid, S *__restrict__ dst)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    if (SOLID && solid[n]) return;
+    Nbr nb;
+    neighbours(g, n, nb);
+    double v[27];
+    sfor<0, 27>([&](auto TT) {
+        constexpr int t = decltype(TT)::value;
+        double val = f[static_cast<size_t>(pop_of_slot(t)) * g.N + n];
+        if constexpr (Traits<S>::kDev) val -= weight_of_slot<double>(t);
+        v[t] = val;
+    });
+    scatter<S, CHECK, SOLID>(dst, g.N, n, nb, solid, v);
+}
+
+// f = f_eq(rho0, u0): the generalized equilibrium (NM)^-1 T_eq, computed in FP64
+// as the reconstruction of T_eq - N(u) M w.
+template <typename S, bool CHECK, bool SOLID>
+__global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, const uint8_t *__restrict__ solid,
+                                                 const double *__restrict__ rho0, const double *__restrict__ u0)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    if (SOLID && solid[n]) return;
+    Nbr nb;
+    neighbours(g, n, nb);
+    const double drho = rho0 ? rho0[n] - 1.0 : 0.0;
+    const double ux = u0 ? u0[n] : 0.0;
+    const double uy = u0 ? u0[g.N + n] : 0.0;
+    const double uz = u0 ? u0[2 * static_cast<size_t>(g.N) + n] : 0.0;
+    const AxisU<double> X(ux), Y(uy), Z(uz);
+    double v[27];
+    equilibrium_moments(v, drho, X, Y, Z);
+    reconstruct(v, ux, uy, uz);
+    if constexpr (!Traits<S>::kDev)
+        sfor<0, 27>([&](auto T) { v[decltype(T)::value] += weight_of_slot<double>(decltype(T)::value); });
+    scatter<S, CHECK, SOLID>(dst, g.N, n, nb, solid, v);
+}
+
+// ------------------------------------------------------------------ adjoint
+// Rates whose adjoint is accumulated: s2 ... s6 (indices 2..9); s0 and s1 act on
+// conserved moments and have zero derivative.
+constexpr int kAdjRates = 8;
+
+// One adjoint step on one node per thread (grid-stride).  Recomputes the forward
+// collision from the state at t, gathers lambda(t+1) along +e (the transpose of
+// the pull), applies the transposed per-node Jacobian and writes lambda(t).
+template <typename S, bool CHECK, bool SOLID, bool FIELD>
+__global__ __launch_bounds__(kBlock) void k_adjoint(const S *__restrict__ state, Geom g,
+                                                    const uint8_t *__restrict__ solid,
+                                                    const typename Traits<S>::R *__restrict__ field,
+                                                    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt,
+                                                    const typename Traits<S>::R *__restrict__ lam_next,
+                                                    typename Traits<S>::R *__restrict__ lam_out,
+                                                    typename Traits<S>::R *__restrict__ dJdF,
+                                                    double *__restrict__ partials)
+{
+    using R = typename Traits<S>::R;
+    constexpr R cs2 = R(1.0 / 3.0), cs4 = R(1.0 / 9.0);
+    double gs[kAdjRates] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.N; n += gridDim.x * kBlock) {
+        if (SOLID && solid[n]) {
+            for (int i = 0; i < 27; ++i) lam_out[static_cast<size_t>(i) * g.N + n] = R(0);
+            continue;
+        }
+        Nbr nb;
+        neighbours(g, n, nb);
+        // ---- forward recomputation
+        R tt[27];
+        gather<S, CHECK, SOLID, false>(state, g.N, n, nb, solid, tt);
+        if constexpr (!Traits<S>::kDev)
+            sfor<0, 27>([&](auto T) { tt[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+        raw_moments(tt);
+        const R drho = tt[slot(0, 0, 0)];
+        const R rho = R(1) + drho;
+        const R inv_rho = R(1) / rho;
+        R Fx, Fy, Fz;
+        force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+        const R ux = (tt[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho;
+        const R uy = (tt[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho;
+        const R uz = (tt[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho;
+        central_shift(tt, ux, uy, uz);  // tt = central moments of d
+        const AxisU<R> X(ux), Y(uy), Z(uz);
+        R ts[27];  // post-collision raw moments T* (full, not deviations)
+        sfor<0, 27>([&](auto T) { ts[decltype(T)::value] = tt[decltype(T)::value]; });
+        collide(ts, drho, X, Y, Z, Fx, Fy, Fz, rt);
+        central_unshift(ts, ux, uy, uz);
+        sfor<0, 27>([&](auto T) {
+            constexpr int t = decltype(T)::value;
+            constexpr R E = R(e_of(sa(t)) * e_of(sb(t)) * e_of(sc(t)));
+            if constexpr (E != R(0)) ts[t] += E;
+        });
+        // full central moments T~ = tt + c (x) c (x) c
+        sfor<0, 27>([&](auto T) {
+            constexpr int t = decltype(T)::value;
+            tt[t] += cw_term<sa(t), sb(t), sc(t)>(X, Y, Z);
+        });
+
+        // ---- adjoint: a = dJ/df*(x), gathered along +e
+        R a[27];
+        gather<R, CHECK, SOLID, true>(lam_next, g.N, n, nb, solid, a);
+        reconstruct_raw_T(a);  // a = M^-T a  (adjoint of T*)
+        R ubx = lowered_dot<0>(a, ts), uby = lowered_dot<1>(a, ts), ubz = lowered_dot<2>(a, ts);
+        unshift_T(a, ux, uy, uz);  // a = adjoint of T~*
+
+        // collision backward
+        R rhob = a[slot(0, 0, 0)];
+        R Fbx = R(0.5) * a[slot(1, 0, 0)], Fby = R(0.5) * a[slot(0, 1, 0)], Fbz = R(0.5) * a[slot(0, 0, 1)];
+        a[slot(0, 0, 0)] = R(0);
+        a[slot(1, 0, 0)] = R(0);
+        a[slot(0, 1, 0)] = R(0);
+        a[slot(0, 0, 1)] = R(0);
+        sfor<0, 27>([&](auto T) {
+            constexpr int t = decltype(T)::value;
+            constexpr int m = sa(t), nn = sb(t), p = sc(t);
+            constexpr int ones = (m == 1) + (nn == 1) + (p == 1);
+            constexpr int order = m + nn + p;
+            if constexpr (order >= 2 && !(order == 2 && ones == 0)) {
+                constexpr int k = rate_of(m, nn, p);
+                constexpr R E = R(e_of(m) * e_of(nn) * e_of(p));
+                const R y = a[t];
+                // R = rho E - T~ - C/2
+                R r = -tt[t];
+                if constexpr (ones == 0) r = fma(rho, E, r);
+                if constexpr (ones == 1) {
+                    constexpr R cf = order == 3 ? cs2 : cs4;
+                    const R Fa = m == 1 ? Fx : (nn == 1 ? Fy : Fz);
+                    r = fma(R(-0.5) * cf, Fa, r);
+                    const R g = rt.hs[k] * cf * y;
+                    if constexpr (m == 1) Fbx += g;
+                    else if constexpr (nn == 1) Fby += g;
+                    else Fbz += g;
+                }
+                gs[k - 2] += static_cast<double>(y * r);
+                if constexpr (ones == 0) rhob = fma(rt.s[k] * E, y, rhob);
+                a[t] = fma(-rt.s[k], y, y);
+            }
+        });
+        {
+            constexpr int ix = slot(2, 0, 0), iy = slot(0, 2, 0), iz = slot(0, 0, 2);
+            const R yx = a[ix], yy = a[iy], yz = a[iz];
+            const R rx = fma(rho, cs2, -tt[ix]), ry = fma(rho, cs2, -tt[iy]), rz = fma(rho, cs2, -tt[iz]);
+            const R ysum = yx + yy + yz, rsum = rx + ry + rz;
+            const R tr = rt.sm * ysum;
+            const R sx = fma(rt.s[R_S2], yx, tr), sy = fma(rt.s[R_S2], yy, tr), sz = fma(rt.s[R_S2], yz, tr);
+            a[ix] = yx - sx;
+            a[iy] = yy - sy;
+            a[iz] = yz - sz;
+            rhob = fma(cs2, sx + sy + sz, rhob);
+            const double third = static_cast<double>(ysum * rsum) / 3.0;
+            gs[R_S2 - 2] += static_cast<double>(yx * rx + yy * ry + yz * rz) - third;
+            gs[R_S2B - 2] += third;
+        }
+        ubx -= lowered_dot<0>(a, tt);
+        uby -= lowered_dot<1>(a, tt);
+        ubz -= lowered_dot<2>(a, tt);
+        shift_T(a, ux, uy, uz);  // a = adjoint of T (raw moments)
+        // u = (j + F/2) / rho
+        a[slot(1, 0, 0)] += ubx * inv_rho;
+        a[slot(0, 1, 0)] += uby * inv_rho;
+        a[slot(0, 0, 1)] += ubz * inv_rho;
+        Fbx = fma(R(0.5) * inv_rho, ubx, Fbx);
+        Fby = fma(R(0.5) * inv_rho, uby, Fby);
+        Fbz = fma(R(0.5) * inv_rho, ubz, Fbz);
+        rhob -= (ubx * ux + uby * uy + ubz * uz) * inv_rho;
+        a[slot(0, 0, 0)] += rhob;
+        raw_moments_T(a);  // lambda(t) = M^T a
+
+        sfor<0, 27>([&](auto TT) {
+            constexpr int t = decltype(TT)::value;
+            lam_out[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = a[t];
+        });
+        if (dJdF) {
+            dJdF[n] += Fbx;
+            dJdF[g.N + n] += Fby;
+            dJdF[2 * static_cast<size_t>(g.N) + n] += Fbz;
+        }
+    }
+    block_reduce_store<kAdjRates>(gs, partials + static_cast<size_t>(blockIdx.x) * kAdjRates);
+}
+
+// Loss J = 1/2 sum_fluid |u - u_t|^2 and its seed lambda = dJ/df; adds dJ/dF (direct).
+template <typename S, bool CHECK, bool SOLID, bool FIELD>
+__global__ __launch_bounds__(kBlock) void k_loss(const S *__restrict__ state, Geom g, const uint8_t *__restrict__ solid,
+                                                 const typename Traits<S>::R *__restrict__ field,
+                                                 Forcing<typename Traits<S>::R> fo,
+                                                 const typename Traits<S>::R *__restrict__ u_target,
+                                                 typename Traits<S>::R *__restrict__ lam_out,
+                                                 typename Traits<S>::R *__restrict__ dJdF, double *__restrict__ partials)
+{
+    using R = typename Traits<S>::R;
+    double acc[1] = {0.0};
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.N; n += gridDim.x * kBlock) {
+        if (SOLID && solid[n]) {
+            for (int i = 0; i < 27; ++i) lam_out[static_cast<size_t>(i) * g.N + n] = R(0);
+            continue;
+        }
+        Nbr nb;
+        neighbours(g, n, nb);
+        R v[27];
+        gather<S, CHECK, SOLID, false>(state, g.N, n, nb, solid, v);
+        if constexpr (!Traits<S>::kDev)
+            sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+        raw_moments(v);
+        R Fx, Fy, Fz;
+        force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+        const R inv_rho = R(1) / (R(1) + v[slot(0, 0, 0)]);
+        const R ux = (v[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho;
+        const R uy = (v[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho;
+        const R uz = (v[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho;
+        const R dx = ux - u_target[n], dy = uy - u_target[g.N + n], dz = uz - u_target[2 * static_cast<size_t>(g.N) + n];
+        acc[0] += 0.5 * (static_cast<double>(dx) * dx + static_cast<double>(dy) * dy + static_cast<double>(dz) * dz);
+        // dJ/df_i = sum_a d_a (e_ia - u_a) / rho
+        const R bx = dx * inv_rho, by = dy * inv_rho, bz = dz * inv_rho;
+        const R base = -(bx * ux + by * uy + bz * uz);
+        sfor<0, 27>([&](auto TT) {
+            constexpr int t = decltype(TT)::value;
+            R val = base;
+            if constexpr (sa(t) == 2) val += bx;
+            if constexpr (sa(t) == 0) val -= bx;
+            if constexpr (sb(t) == 2) val += by;
+            if constexpr (sb(t) == 0) val -= by;
+            if constexpr (sc(t) == 2) val += bz;
+            if constexpr (sc(t) == 0) val -= bz;
+            lam_out[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = val;
+        });
+        if (dJdF) {
+            dJdF[n] += R(0.5) * bx;
+            dJdF[g.N + n] += R(0.5) * by;
+            dJdF[2 * static_cast<size_t>(g.N) + n] += R(0.5) * bz;
+        }
+    }
+    block_reduce_store<1>(acc, partials + blockIdx.x);
+}
+
+// ------------------------------------------------------------------ plain copy (checkpoints)
+__global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n16)
+{
+    for (size_t k = blockIdx.x * static_cast<size_t>(kBlock) + threadIdx.x; k < n16;
+         k += static_cast<size_t>(gridDim.x) * kBlock)
+        dst[k] = src[k];
+}
+
+__global__ void k_copy_tail(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, size_t n)
+{
+    const size_t k = threadIdx.x;
+    if (k < n) dst[k] = src[k];
+}
+
+}  // namespace clbm

@@ -1,0 +1,373 @@
+// Per-node arithmetic of the D3Q27 cascaded LBM (arXiv:1801.04586, Sec. II),
+// written for registers: every loop is unrolled at compile time and every array
+// index is a constant, so a node's 27 values never leave VGPRs.
+//
+// Tensor-slot convention.  A node's 27 values live in v[9*a + 3*b + c].
+//  - As populations, (a, b, c) = (e_x + 1, e_y + 1, e_z + 1).
+//  - As moments, (a, b, c) = (m, n, p), the exponents of k_mnp (Eq. (2)).
+// The moment set of Eq. (12) is exactly {0,1,2}^3, so M (Eq. (14)) and the shift
+// N(u) (Eq. (4)) are tensor products of one 3x3 matrix per axis:
+//   M1 = [[1,1,1],[-1,0,1],[1,0,1]] on (f(e=-1), f(0), f(+1)),
+//   N1(u) = [[1,0,0],[-u,1,0],[u^2,-2u,1]],  N1(u)^-1 = N1(-u),
+// and M, M^-1, N, N^-1 are applied as three passes of nine 3-vectors each.
+// This is the split of the reconstruction into N^-1 then M^-1 that Sec. II B
+// recommends, carried one level further (per axis).
+//
+// Deviation form.  Populations are handled as deviations d = f - w from the
+// rest-state weights w = w1 (x) w1 (x) w1, w1 = (1/6, 2/3, 1/6).  The raw moments
+// of w are E = e (x) e (x) e with e = (1, 0, 1/3), which are also the per-unit-
+// density equilibria of Eq. (15).  With rho = 1 + drho and the central moments of
+// w about u equal to c(ux) (x) c(uy) (x) c(uz), c(u) = (1, -u, 1/3 + u^2), every
+// quantity the collision needs is formed from small numbers (drho, u, F, d), so
+// FP32 arithmetic on FP32/FP16/BF16 deviations keeps its relative precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace clbm {
+
+// ------------------------------------------------------------------ compile-time loops
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+__host__ __device__ constexpr int slot(int a, int b, int c) { return 9 * a + 3 * b + c; }
+__host__ __device__ constexpr int sa(int t) { return t / 9; }
+__host__ __device__ constexpr int sb(int t) { return (t / 3) % 3; }
+__host__ __device__ constexpr int sc(int t) { return t % 3; }
+
+// Population index in the order of Eq. (1) for the velocity held in tensor slot t.
+__host__ __device__ constexpr int pop_of_slot(int t)
+{
+    constexpr int tab[27] = {26, 10, 22, 14, 2, 12, 24, 8, 20, 18, 4, 16, 6, 0,
+                             5,  17, 3,  15, 25, 9, 21, 13, 1, 11, 23, 7, 19};
+    return tab[t];
+}
+
+// Velocity set of Eq. (1), typed here to cross-check the table above at compile time.
+namespace eq1 {
+constexpr int ex[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr int ey[27] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, 1, -1, -1, 1, 1, -1, -1};
+constexpr int ez[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+constexpr bool table_ok()
+{
+    for (int t = 0; t < 27; ++t) {
+        const int i = pop_of_slot(t);
+        if (ex[i] != sa(t) - 1 || ey[i] != sb(t) - 1 || ez[i] != sc(t) - 1) return false;
+    }
+    return true;
+}
+static_assert(table_ok(), "slot -> population table disagrees with Eq. (1)");
+}  // namespace eq1
+
+// Rest-state weight of the velocity in slot t: product of (1/6, 2/3, 1/6) per axis.
+template <typename R>
+__host__ __device__ constexpr R weight_of_slot(int t)
+{
+    constexpr double w1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+    return R(w1[sa(t)] * w1[sb(t)] * w1[sc(t)]);
+}
+
+// e = (1, 0, 1/3): raw moments of w1, i.e. the equilibria of Eq. (15) per unit density.
+__host__ __device__ constexpr double e_of(int k) { return k == 0 ? 1.0 : (k == 1 ? 0.0 : 1.0 / 3.0); }
+
+// ------------------------------------------------------------------ relaxation rates
+// Eq. (13).  s[] = {s0, s1, s2 (= s_nu), s2b, s3, s3b, s4, s4b, s5, s6}; hs = 1 - s/2;
+// sm = s_- = (s2b - s2)/3 couples the three normal second moments.
+template <typename R>
+struct Rates {
+    R s[10];
+    R hs[10];
+    R sm;
+};
+
+enum { R_S0 = 0, R_S1, R_S2, R_S2B, R_S3, R_S3B, R_S4, R_S4B, R_S5, R_S6 };
+
+// Rate index of moment (m, n, p) of Eq. (12) outside the conserved slots and the
+// normal-stress block.
+__host__ __device__ constexpr int rate_of(int m, int n, int p)
+{
+    const int ones = (m == 1) + (n == 1) + (p == 1);
+    const int order = m + n + p;
+    if (order == 2) return R_S2;               // k110, k101, k011 (s_nu)
+    if (order == 3 && ones == 1) return R_S3;  // k120 ... k021
+    if (order == 3) return R_S3B;              // k111
+    if (order == 4 && ones == 0) return R_S4;  // k220, k202, k022
+    if (order == 4) return R_S4B;              // k211, k121, k112
+    if (order == 5) return R_S5;               // k122, k212, k221
+    return R_S6;                               // k222
+}
+
+// ------------------------------------------------------------------ per-axis passes
+// Apply op(v0, v1, v2) to the nine triples along axis AX (0 = x, 1 = y, 2 = z).
+template <int AX, typename R, typename Op>
+__device__ __forceinline__ void axis_pass(R (&v)[27], Op &&op)
+{
+    sfor<0, 9>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr int o1 = k / 3, o2 = k % 3;
+        constexpr int base = AX == 0 ? slot(0, o1, o2) : (AX == 1 ? slot(o1, 0, o2) : slot(o1, o2, 0));
+        constexpr int st = AX == 0 ? 9 : (AX == 1 ? 3 : 1);
+        op(v[base], v[base + st], v[base + 2 * st]);
+    });
+}
+
+// M1: (f(-1), f(0), f(+1)) -> (k0, k1, k2) raw moments along one axis.
+template <typename R>
+__device__ __forceinline__ void raw_moments(R (&v)[27])
+{
+    auto op = [](R &a, R &b, R &c) {
+        const R k0 = a + b + c, k1 = c - a, k2 = c + a;
+        a = k0;
+        b = k1;
+        c = k2;
+    };
+    axis_pass<2>(v, op);
+    axis_pass<1>(v, op);
+    axis_pass<0>(v, op);
+}
+
+// N1(u): raw (k0, k1, k2) -> central (k0, k1 - u k0, k2 - 2u k1 + u^2 k0).
+template <typename R>
+__device__ __forceinline__ void shift_pass_op(R &k0, R &k1, R &k2, R u)
+{
+    const R t1 = fma(-u, k0, k1);
+    k2 = fma(-u, k1 + t1, k2);
+    k1 = t1;
+}
+
+template <typename R>
+__device__ __forceinline__ void central_shift(R (&v)[27], R ux, R uy, R uz)
+{
+    axis_pass<0>(v, [=](R &a, R &b, R &c) { shift_pass_op(a, b, c, ux); });
+    axis_pass<1>(v, [=](R &a, R &b, R &c) { shift_pass_op(a, b, c, uy); });
+    axis_pass<2>(v, [=](R &a, R &b, R &c) { shift_pass_op(a, b, c, uz); });
+}
+
+// N1(-u): central (k0, k1, k2) -> raw (k0, k1 + u k0, k2 + 2u k1 + u^2 k0).
+template <typename R>
+__device__ __forceinline__ void unshift_pass_op(R &k0, R &k1, R &k2, R u)
+{
+    const R r1 = fma(u, k0, k1);
+    k2 = fma(u, k1 + r1, k2);
+    k1 = r1;
+}
+
+template <typename R>
+__device__ __forceinline__ void central_unshift(R (&v)[27], R ux, R uy, R uz)
+{
+    axis_pass<0>(v, [=](R &a, R &b, R &c) { unshift_pass_op(a, b, c, ux); });
+    axis_pass<1>(v, [=](R &a, R &b, R &c) { unshift_pass_op(a, b, c, uy); });
+    axis_pass<2>(v, [=](R &a, R &b, R &c) { unshift_pass_op(a, b, c, uz); });
+}
+
+// N1(-u) followed by M1^-1: central (k0, k1, k2) -> populations
+// (f(-1), f(0), f(+1)) = ((r2 - r1)/2, k0 - r2, (r2 + r1)/2).
+template <typename R>
+__device__ __forceinline__ void reconstruct(R (&v)[27], R ux, R uy, R uz)
+{
+    auto mk = [](R u) {
+        return [=](R &k0, R &k1, R &k2) {
+            const R r1 = fma(u, k0, k1);
+            const R r2 = fma(u, k1 + r1, k2);
+            const R h2 = R(0.5) * r2;
+            const R fm = fma(R(-0.5), r1, h2);
+            const R fp = fma(R(0.5), r1, h2);
+            const R f0 = k0 - r2;
+            k0 = fm;
+            k1 = f0;
+            k2 = fp;
+        };
+    };
+    axis_pass<0>(v, mk(ux));
+    axis_pass<1>(v, mk(uy));
+    axis_pass<2>(v, mk(uz));
+}
+
+// ------------------------------------------------------------------ per-node velocity factors
+// For one axis: q = c - e and c, the central moments of w1 about u, per exponent k.
+template <typename R>
+struct AxisU {
+    R u, u2, c2;  // u, u^2, 1/3 + u^2
+    __device__ __forceinline__ explicit AxisU(R u_) : u(u_), u2(u_ * u_), c2(R(1.0 / 3.0) + u_ * u_) {}
+    template <int K>
+    __device__ __forceinline__ R q() const { return K == 0 ? R(0) : (K == 1 ? -u : u2); }
+    template <int K>
+    __device__ __forceinline__ R c() const { return K == 0 ? R(1) : (K == 1 ? -u : c2); }
+};
+
+// G(m,n,p) = c_m c_n c_p - e_m e_n e_p, expanded so that no O(1) terms cancel:
+// q_m c_n c_p + e_m q_n c_p + e_m e_n q_p.
+template <int M, int N, int P, typename R>
+__device__ __forceinline__ R g_term(const AxisU<R> &X, const AxisU<R> &Y, const AxisU<R> &Z)
+{
+    R g = R(0);
+    if constexpr (M != 0) g = X.template q<M>() * Y.template c<N>() * Z.template c<P>();
+    if constexpr (M != 1 && N != 0) g += R(e_of(M)) * Y.template q<N>() * Z.template c<P>();
+    if constexpr (M != 1 && N != 1 && P != 0) g += R(e_of(M) * e_of(N)) * Z.template q<P>();
+    return g;
+}
+
+// Full central moment of w about u: c_m c_n c_p.
+template <int M, int N, int P, typename R>
+__device__ __forceinline__ R cw_term(const AxisU<R> &X, const AxisU<R> &Y, const AxisU<R> &Z)
+{
+    return X.template c<M>() * Y.template c<N>() * Z.template c<P>();
+}
+
+// ------------------------------------------------------------------ collision (Eq. (5))
+// On entry v holds the central moments of d about u; on exit the post-collision
+// central moments minus those of w, T~* - N(u) M w, ready for reconstruct().
+//   T~*   = T~ - S (T~ - rho E) + (I - S/2) C          (Eq. (5), (15), (16))
+//   slot 000: T~* = rho; first-order slots: T~* = F/2 (the conserved moments;
+//   their rates s0, s1 drop out exactly).
+template <typename R>
+__device__ __forceinline__ void collide(R (&v)[27], R drho, const AxisU<R> &X, const AxisU<R> &Y,
+                                        const AxisU<R> &Z, R Fx, R Fy, R Fz, const Rates<R> &s)
+{
+    constexpr R cs2 = R(1.0 / 3.0), cs4 = R(1.0 / 9.0);
+    sfor<0, 27>([&](auto T) {
+        constexpr int t = decltype(T)::value;
+        constexpr int m = sa(t), n = sb(t), p = sc(t);
+        constexpr int ones = (m == 1) + (n == 1) + (p == 1);
+        constexpr int order = m + n + p;
+        if constexpr (order == 0) {
+            v[t] = drho;
+        } else if constexpr (order == 1) {
+            // T~*_100 = F_x/2, minus the w part c_1(u_x) = -u_x
+            v[t] = m == 1 ? fma(R(0.5), Fx, X.u) : (n == 1 ? fma(R(0.5), Fy, Y.u) : fma(R(0.5), Fz, Z.u));
+        } else if constexpr (order == 2 && ones == 0) {
+            // normal second moments: relaxed below as a block
+        } else {
+            constexpr int k = rate_of(m, n, p);
+            constexpr R E = R(e_of(m) * e_of(n) * e_of(p));
+            R neq = v[t] + g_term<m, n, p>(X, Y, Z);
+            if constexpr (ones == 0) neq = fma(-drho, E, neq);
+            R out = fma(-s.s[k], neq, v[t]);
+            if constexpr (ones == 1) {
+                // Eq. (16): F_alpha c_s^(m+n+p-1) in the slot whose single odd exponent is alpha
+                constexpr R cf = order == 3 ? cs2 : cs4;
+                const R Fa = m == 1 ? Fx : (n == 1 ? Fy : Fz);
+                out = fma(s.hs[k] * cf, Fa, out);
+            }
+            v[t] = out;
+        }
+    });
+    // block of Eq. (13) on (k200, k020, k002): deviators at s2, trace at s2b
+    constexpr int ix = slot(2, 0, 0), iy = slot(0, 2, 0), iz = slot(0, 0, 2);
+    const R nx = v[ix] + X.u2 - drho * cs2;
+    const R ny = v[iy] + Y.u2 - drho * cs2;
+    const R nz = v[iz] + Z.u2 - drho * cs2;
+    const R tr = s.sm * (nx + ny + nz);
+    v[ix] -= fma(s.s[R_S2], nx, tr);
+    v[iy] -= fma(s.s[R_S2], ny, tr);
+    v[iz] -= fma(s.s[R_S2], nz, tr);
+}
+
+// Deviation of the generalized equilibrium (Sec. II B) in central-moment space:
+// T_eq - N(u) M w = drho E - G.  Feeding it to reconstruct() gives f_eq - w.
+template <typename R>
+__device__ __forceinline__ void equilibrium_moments(R (&v)[27], R drho, const AxisU<R> &X, const AxisU<R> &Y,
+                                                    const AxisU<R> &Z)
+{
+    sfor<0, 27>([&](auto T) {
+        constexpr int t = decltype(T)::value;
+        constexpr int m = sa(t), n = sb(t), p = sc(t);
+        constexpr R E = R(e_of(m) * e_of(n) * e_of(p));
+        v[t] = drho * E - g_term<m, n, p>(X, Y, Z);
+    });
+}
+
+// ------------------------------------------------------------------ transposed passes (adjoint)
+// (M1^-1)^T: adjoint of populations (a-, a0, a+) -> adjoint of raw (r0, r1, r2).
+template <typename R>
+__device__ __forceinline__ void reconstruct_raw_T(R (&v)[27])
+{
+    auto op = [](R &am, R &a0, R &ap) {
+        const R r0 = a0;
+        const R r1 = R(0.5) * (ap - am);
+        const R r2 = fma(R(0.5), am + ap, -a0);
+        am = r0;
+        a0 = r1;
+        ap = r2;
+    };
+    axis_pass<0>(v, op);
+    axis_pass<1>(v, op);
+    axis_pass<2>(v, op);
+}
+
+// N1(-u)^T: adjoint of raw (r0, r1, r2) -> adjoint of central (k0, k1, k2).
+template <typename R>
+__device__ __forceinline__ void unshift_T(R (&v)[27], R ux, R uy, R uz)
+{
+    auto mk = [](R u) {
+        return [=](R &r0, R &r1, R &r2) {
+            const R k0 = fma(u, fma(u, r2, r1), r0);  // r0 + u r1 + u^2 r2
+            const R k1 = fma(R(2) * u, r2, r1);        // r1 + 2u r2
+            r0 = k0;
+            r1 = k1;
+        };
+    };
+    axis_pass<0>(v, mk(ux));
+    axis_pass<1>(v, mk(uy));
+    axis_pass<2>(v, mk(uz));
+}
+
+// N1(u)^T: adjoint of central (k0, k1, k2) -> adjoint of raw (r0, r1, r2).
+template <typename R>
+__device__ __forceinline__ void shift_T(R (&v)[27], R ux, R uy, R uz)
+{
+    auto mk = [](R u) {
+        return [=](R &k0, R &k1, R &k2) {
+            const R r0 = fma(-u, fma(-u, k2, k1), k0);  // k0 - u k1 + u^2 k2
+            const R r1 = fma(R(-2) * u, k2, k1);         // k1 - 2u k2
+            k0 = r0;
+            k1 = r1;
+        };
+    };
+    axis_pass<0>(v, mk(ux));
+    axis_pass<1>(v, mk(uy));
+    axis_pass<2>(v, mk(uz));
+}
+
+// M1^T: adjoint of raw (k0, k1, k2) -> adjoint of populations (f(-1), f(0), f(+1)).
+template <typename R>
+__device__ __forceinline__ void raw_moments_T(R (&v)[27])
+{
+    auto op = [](R &k0, R &k1, R &k2) {
+        const R fm = k0 - k1 + k2, f0 = k0, fp = k0 + k1 + k2;
+        k0 = fm;
+        k1 = f0;
+        k2 = fp;
+    };
+    axis_pass<0>(v, op);
+    axis_pass<1>(v, op);
+    axis_pass<2>(v, op);
+}
+
+// sum_t abar[t] * m_t^AX * w[t - e_AX]: the derivative of a per-axis shift with
+// respect to the shift velocity, d/du (N1(-u)) = D N1(-u) and d/du N1(u) = -D N1(u)
+// with (D v)_m = m v_{m-1}, contracted with the adjoint.
+template <int AX, typename R>
+__device__ __forceinline__ R lowered_dot(const R (&abar)[27], const R (&w)[27])
+{
+    R acc = R(0);
+    sfor<0, 27>([&](auto T) {
+        constexpr int t = decltype(T)::value;
+        constexpr int k = AX == 0 ? sa(t) : (AX == 1 ? sb(t) : sc(t));
+        constexpr int st = AX == 0 ? 9 : (AX == 1 ? 3 : 1);
+        if constexpr (k == 1) acc = fma(abar[t], w[t - st], acc);
+        if constexpr (k == 2) acc = fma(R(2) * abar[t], w[t - st], acc);
+    });
+    return acc;
+}
+
+}  // namespace clbm
