@@ -1,0 +1,362 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D3Q27 cascaded-LBM step on one MI355X.
+
+Workload (the roofline and precision case): Kolmogorov-forced flow on a 512^3
+periodic lattice, F_x = 1e-5 sin(2 pi 4 y / 512) as a per-node FP32 field,
+nu = 0.005, seeded U(-1e-3, 1e-3) velocity perturbation, populations stored as
+FP32 deviations f - w with FP32 arithmetic.  A "step" is one time step of the
+whole lattice (one launch of the fused collide-and-stream kernel); the metric
+is MLUPS (million lattice-node updates per second) and the fraction of the
+HBM roofline.  Inputs are resident in HBM before the timed region.
+
+Also reported from the same run (each timed with HIP events, trimmed mean of
+9 repetitions as in the paper's Table I protocol): the FP64, FP16 and BF16
+storage variants on the same lattice, the plain kernel on the 128^3
+Taylor-Green case, the adjoint step on a 256x128x128 porous crop, the
+velocity error of every storage type against FP64 after 500 steps, and the
+FP64 CPU oracle on a bounded sample of the same workload.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD datasheet
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_step_f32_kolmogorov512.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_04586_amd", "csrc", f) for f in ("node.hpp", "kernels.hpp")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_node(storage: str, field: bool, solid: bool) -> int:
+    size = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
+    b = 2 * 27 * size
+    if field:
+        b += 3 * (8 if storage == "f64" else 4)
+    if solid:
+        b += 1
+    return b
+
+
+def trimmed_mean(xs):
+    xs = sorted(xs)
+    if len(xs) > 2:
+        xs = xs[1:-1]
+    return sum(xs) / len(xs)
+
+
+def time_steps(torch, lat, steps, reps=9):
+    """Trimmed-mean ms per step over `reps` repetitions of `steps` steps (HIP events)."""
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        lat.step(steps)
+        b.record()
+        b.synchronize()
+        out.append(a.elapsed_time(b) / steps)
+    return trimmed_mean(out)
+
+
+def kolmogorov_inputs(dims):
+    import workloads
+
+    u0 = workloads.uniform_random_velocity(dims, 1e-3, workloads.SEED)
+    F = workloads.kolmogorov_force(dims, 1e-5, 4)
+    return u0, F
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--size", type=int, default=512, help="edge of the cubic Kolmogorov lattice")
+    ap.add_argument("--primary-only", action="store_true", help="time only the FP32 step (for profilers)")
+    ap.add_argument("--copy-calibration", action="store_true", help="also run the plain copy kernel (PMC scale)")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1801_04586_amd import Lattice
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = args.size
+    dims = (L, L, L)
+    nodes = L ** 3
+    nu = 0.005
+    rates = workloads.rates(nu)
+    log(f"[bench] Kolmogorov {dims}, nu={nu}, s2={rates[2]:.6f}; generating inputs")
+    u0, F = kolmogorov_inputs(dims)
+    u0_dev = torch.from_numpy(u0).to(dev)
+    F32_dev = torch.from_numpy(F).to(dev, torch.float32)
+    F64_dev = None
+
+    # ------------------------------------------------------------------ primary: FP32 storage
+    lat = Lattice(dims, (0, 0, 0), "f32", rates, force_field=F32_dev, device=dev)
+    lat.init(None, u0_dev)
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    lat.step(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    mlups = nodes * args.steps / wall / 1e6
+    bpn = bytes_per_node("f32", True, False)
+    achieved = bpn * nodes / (kernel_ms * 1e-3) / 1e9
+    log(f"[bench] f32: {ms_per_step:.3f} ms/step wall, {kernel_ms:.3f} ms/kernel, {mlups:.0f} MLUPS, "
+        f"{achieved:.0f} GB/s algorithmic")
+    _, _, tot, nbad = lat.moments(fields=False)
+    if nbad:
+        log(f"[bench] WARNING: {nbad} non-finite nodes")
+
+    if args.copy_calibration:
+        tmp = torch.empty_like(lat.state)
+        for _ in range(5):
+            lat.ctx.copy(lat.state, tmp)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            lat.ctx.copy(lat.state, tmp)
+        c1.record()
+        torch.cuda.synchronize()
+        cms = c0.elapsed_time(c1) / 5
+        log(f"[bench] copy {lat.state.numel() * 4 / 1e9:.2f} GB: {cms:.3f} ms = "
+            f"{2 * lat.state.numel() * 4 / (cms * 1e-3) / 1e9:.0f} GB/s read+write")
+        del tmp
+
+    traffic = None
+    if os.path.exists(PMC_SUMMARY):
+        with open(PMC_SUMMARY) as fh:
+            pmc = json.load(fh)
+        if pmc.get("kernel_src_sha") == kernel_sha() and pmc.get("size") == L:
+            traffic = pmc.get("hbm_bytes_per_launch")
+
+    result = {
+        "metric": "MLUPS (FP32-storage fused D3Q27 cascaded-LBM step) and fraction of HBM roofline",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"kolmogorov_{L}^3",
+            "nodes": nodes,
+            "storage": "f32 deviations f - w",
+            "force": "per-node FP32 field, F0 = 1e-5, k = 4",
+            "nu": nu,
+            "boundaries": "periodic",
+            "bytes_per_node": bpn,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_step<float, periodic, force field>",
+            "kernel_ms": round(kernel_ms, 4),
+            "algorithmic_bytes_per_launch": bpn * nodes,
+        },
+    }
+    if args.primary_only:
+        print(json.dumps(result), flush=True)
+        return
+
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------------ other storage types, same lattice
+    variants = {}
+    if not args.no_variants:
+        for storage in ("f64", "f16", "bf16"):
+            field = F32_dev
+            if storage == "f64":
+                F64_dev = torch.from_numpy(F).to(dev)
+                field = F64_dev
+            lv = Lattice(dims, (0, 0, 0), storage, rates, force_field=field, device=dev)
+            lv.init(None, u0_dev)
+            lv.step(3)
+            ms = time_steps(torch, lv, 10)
+            b = bytes_per_node(storage, True, False)
+            variants[f"kolmogorov_{L}_{storage}"] = {
+                "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4),
+                "bytes_per_node": b, "frac": round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log(f"[bench] {storage}: {ms:.3f} ms/step, {variants[f'kolmogorov_{L}_{storage}']}")
+            lv.close()
+            del lv
+            torch.cuda.empty_cache()
+        variants[f"kolmogorov_{L}_f32"] = {"mlups": round(nodes / (kernel_ms * 1e-3) / 1e6, 1),
+                                           "kernel_ms": round(kernel_ms, 4), "bytes_per_node": bpn,
+                                           "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        f64k = variants[f"kolmogorov_{L}_f64"]["kernel_ms"]
+        result["speedup_f32_over_f64"] = round(f64k / kernel_ms, 3)
+
+        # plain kernel on the 128^3 Taylor-Green case
+        tdims = (128, 128, 128)
+        rho_t, u_t = workloads.taylor_green_3d(tdims, 0.04)
+        for storage in ("f64", "f32"):
+            lt = Lattice(tdims, (0, 0, 0), storage, workloads.rates(0.01), device=dev)
+            lt.init(rho_t, u_t)
+            lt.step(3)
+            ms = time_steps(torch, lt, 50)
+            b = bytes_per_node(storage, False, False)
+            variants[f"taylor_green_128_{storage}"] = {
+                "mlups": round(128 ** 3 / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4), "bytes_per_node": b,
+                "frac": round(b * 128 ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "2 x 226-453 MB working set: partly served by the 256 MB last-level cache"}
+            lt.close()
+
+        # adjoint step on a porous crop (FP32, walls y/z, spheres, per-node force field)
+        adims = (256, 128, 128)
+        mask, _, _ = workloads.porous_spheres(adims, (0, 1, 1), 6.0, 12.0, 0.2, workloads.SEED)
+        Fa = workloads.gaussian_force(adims, 1e-6, workloads.SEED)
+        la = Lattice(adims, (0, 1, 1), "f32", workloads.rates(0.02), force=(2e-6, 0, 0), force_field=Fa, solid=mask,
+                     device=dev)
+        la.init()
+        la.step(5)
+        ut = torch.zeros((3,) + la.shape, dtype=torch.float32, device=dev)
+        lam = torch.empty((27,) + la.shape, dtype=torch.float32, device=dev)
+        lam2 = torch.empty_like(lam)
+        gF = torch.zeros((3,) + la.shape, dtype=torch.float32, device=dev)
+        gs = torch.zeros(10, dtype=torch.float64, device=dev)
+        la.ctx.loss_seed(la.state, ut, lam, gF, None)
+        an = int(np.prod(adims))
+        reps = []
+        for _ in range(9):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(10):
+                la.ctx.adjoint_step(la.state, lam, lam2, gF, gs)
+                lam, lam2 = lam2, lam
+            b.record()
+            b.synchronize()
+            reps.append(a.elapsed_time(b) / 10)
+        ams = trimmed_mean(reps)
+        fwd = time_steps(torch, la, 10)
+        # adjoint bytes per fluid node: state 27x4 + lambda in/out 2x27x4 + dJ/dF rmw 2x3x4 + force 3x4 + mask
+        ab = 27 * 4 * 3 + 24 + 12 + 1
+        variants["adjoint_porous_256x128x128_f32"] = {
+            "adjoint_mlups": round(an / (ams * 1e-3) / 1e6, 1), "adjoint_kernel_ms": round(ams, 4),
+            "with_recompute_mlups": round(an / ((ams + fwd) * 1e-3) / 1e6, 1),
+            "bytes_per_node": ab, "frac": round(ab * an / (ams * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "solid_fraction": round(float(mask.mean()), 4)}
+        log(f"[bench] adjoint: {variants['adjoint_porous_256x128x128_f32']}")
+        la.close()
+        del la, lam, lam2, gF
+        torch.cuda.empty_cache()
+    result["variants"] = variants
+
+    # ------------------------------------------------------------------ accuracy of storage types vs FP64
+    if not args.no_accuracy:
+        steps = 500
+        acc = {}
+        if F64_dev is None:
+            F64_dev = torch.from_numpy(F).to(dev)
+        l64 = Lattice(dims, (0, 0, 0), "f64", rates, force_field=F64_dev, device=dev)
+        l64.init(None, u0_dev)
+        l64.step(steps)
+        _, u64, _, _ = l64.moments()
+        l64.close()
+        del l64
+        torch.cuda.empty_cache()
+        nrm = torch.linalg.vector_norm(u64).item()
+        umax = u64.abs().max().item()
+        for storage in ("f32", "f16", "bf16"):
+            ls = Lattice(dims, (0, 0, 0), storage, rates, force_field=F32_dev, device=dev)
+            ls.init(None, u0_dev)
+            ls.step(steps)
+            _, us, _, nb = ls.moments()
+            d = us - u64
+            acc[storage] = {"l2_rel": float(torch.linalg.vector_norm(d).item() / nrm),
+                            "max_rel": float(d.abs().max().item() / umax), "nonfinite": int(nb)}
+            log(f"[bench] accuracy {storage} after {steps} steps: {acc[storage]}")
+            ls.close()
+            del ls, us, d
+            torch.cuda.empty_cache()
+        acc["reference"] = f"FP64 storage, same inputs, {steps} steps; u_max = {umax:.4e}"
+        result["accuracy_vs_f64"] = acc
+        del u64
+
+    # ------------------------------------------------------------------ CPU oracle on a bounded sample
+    if not args.no_cpu:
+        import oracle
+
+        wd = (128, 128, 32)
+        g = oracle.Geometry(dims, (0, 0, 0), (0, 0, 0), wd)
+        sl = (slice(0, wd[2]), slice(0, wd[1]), slice(0, wd[0]))
+        f0 = oracle.init(g, None, np.ascontiguousarray(u0[(slice(None),) + sl]))
+        Fw = np.ascontiguousarray(F[(slice(None),) + sl])
+        t0 = time.perf_counter()
+        f = oracle.step(g, f0, rates, force_field=Fw)
+        t1 = time.perf_counter() - t0
+        nsteps = max(1, min(50, int(args.cpu_seconds / max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            f = oracle.step(g, f, rates, force_field=Fw)
+        tc = time.perf_counter() - t0
+        wn = int(np.prod(wd))
+        result["cpu_baseline"] = {
+            "value": round(wn * nsteps / tc / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{wd[0]}x{wd[1]}x{wd[2]} window of the {L}^3 Kolmogorov lattice, {nsteps} steps, FP64 dense "
+                      f"27x27 oracle, {tc:.1f} s"}
+        log(f"[bench] cpu baseline: {result['cpu_baseline']}")
+
+    result["context"] = {
+        "paper_cpu": "0.45 MLUPS: C++ CLBM, i7-6500U laptop, 5x101x5 shear wave (Table I), context only",
+        "hbm_peak_gbs": HBM_PEAK_GBS,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,8 +68,14 @@ def lib():
         L.orc_init.argtypes = [ip, dp, dp, dp]
         L.orc_adjoint_step.argtypes = [ip, dp, dp, dp, u8, dp, dp, dp, dp, dp]
         L.orc_loss_seed.argtypes = [ip, dp, dp, u8, dp, dp, dp, dp, dp]
+        L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().orc_num_threads())
 
 
 # --------------------------------------------------------------------------- helpers

@@ -37,6 +37,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 27
 
@@ -705,3 +708,13 @@ int orc_loss_seed(const int *geom, const double *Fu, const double *Ff, const uin
 }
 
 int orc_abi_version(void) { return 1; }
+
+/* Threads the OpenMP loops above use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
