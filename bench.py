@@ -255,6 +255,53 @@ def main():
                 "note": "2 x 226-453 MB working set: partly served by the 256 MB last-level cache"}
             lt.close()
 
+        # porous duct 640x320x320, FP32, walls in y and z, spheres (solid fraction 0.2)
+        pdims = (640, 320, 320)
+        pmask, _, _ = workloads.porous_spheres(pdims, (0, 1, 1), 6.0, 12.0, 0.2, workloads.SEED)
+        lp = Lattice(pdims, (0, 1, 1), "f32", workloads.rates(0.02), force=(2e-6, 0, 0), solid=pmask, device=dev)
+        lp.init()
+        lp.step(3)
+        ms = time_steps(torch, lp, 10)
+        pn = int(np.prod(pdims))
+        fluid = int((pmask == 0).sum())
+        pb = 2 * 27 * 4 * fluid + pn  # populations of fluid nodes + the solid mask
+        variants["porous_640x320x320_f32"] = {
+            "mlups": round(pn / (ms * 1e-3) / 1e6, 1), "mflups_fluid": round(fluid / (ms * 1e-3) / 1e6, 1),
+            "kernel_ms": round(ms, 4), "bytes_per_node": round(pb / pn, 2),
+            "frac": round(pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "solid_fraction": round(1 - fluid / pn, 4)}
+        log(f"[bench] porous: {variants['porous_640x320x320_f32']}")
+        lp.close()
+        del lp
+        torch.cuda.empty_cache()
+
+        # end-to-end gradient on the adjoint channel case: 64^3, T = 200, checkpoint every 20, FP32
+        from paper_1801_04586_amd.adjoint import flow_loss
+
+        cdims, T, K = (64, 64, 64), 200, 20
+        Fc = workloads.gaussian_force(cdims, 1e-6, workloads.SEED)
+        lc = Lattice(cdims, (0, 1, 0), "f32", workloads.rates(0.05), force_field=Fc, device=dev)
+        lc.init()
+        s0 = lc.state.clone()
+        utc = torch.from_numpy(workloads.channel_target(cdims, (0, 1, 0), 1e-4)).to(dev, torch.float32)
+        Ft = torch.from_numpy(Fc).to(dev, torch.float32)
+        st = torch.from_numpy(workloads.rates(0.05))
+        times = []
+        for _ in range(3):
+            Fr, sr = Ft.clone().requires_grad_(True), st.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            flow_loss(Fr, sr, lc, s0, utc, T, K).backward()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        cn = int(np.prod(cdims))
+        tbest = min(times)
+        variants["adjoint_channel_64_f32_T200_K20"] = {
+            "gradient_seconds": round(tbest, 4),
+            "node_updates_per_s_M": round(cn * T * 3 / tbest / 1e6, 1),
+            "note": "forward T steps + recompute T steps + T adjoint steps, 64^3 (cache-resident, launch-bound)"}
+        log(f"[bench] adjoint channel: {variants['adjoint_channel_64_f32_T200_K20']}")
+        lc.close()
+
         # adjoint step on a porous crop (FP32, walls y/z, spheres, per-node force field)
         adims = (256, 128, 128)
         mask, _, _ = workloads.porous_spheres(adims, (0, 1, 1), 6.0, 12.0, 0.2, workloads.SEED)

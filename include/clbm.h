@@ -40,7 +40,8 @@
  *    CLBM_F32, CLBM_F16, CLBM_BF16 store the deviation f_i - w_i from the
  *    rest-state weights (8/27, 2/27, 1/54, 1/216), rounded to nearest even,
  *    arithmetic in FP32.
- * Entries belonging to solid nodes are never read or written by the step.
+ * Entries belonging to solid nodes are never read; the step stores unspecified
+ * values there (whole cache lines are written for speed).
  */
 #ifndef CLBM_H
 #define CLBM_H
@@ -87,7 +88,8 @@ typedef struct clbm_desc {
     double force_uniform[3];
     double force_scale;
     const void *force;
-    /* Solid mask: device uint8 [N], nonzero = solid, or NULL (all fluid). */
+    /* Solid mask: device uint8 [N], nonzero = solid, or NULL (all fluid).  Read
+     * once, by clbm_create, which derives the context's link table from it. */
     const uint8_t *solid;
 } clbm_desc;
 
@@ -102,10 +104,13 @@ const char *clbm_strerror(int status);
 /* Text of the last error on this context (may include HIP's message).  Never NULL. */
 const char *clbm_last_error(const clbm_ctx *ctx);
 
-/* Create a context for the lattice *desc (copied; the force and solid buffers
- * are referenced, not copied, and must outlive their use).  stream: hipStream_t
- * or NULL.  Allocates only small device scratch for reductions (< 1 MiB).
- * *out is set to NULL on error. */
+/* Create a context for the lattice *desc (copied; the force buffer is
+ * referenced, not copied, and must outlive its use).  stream: hipStream_t or
+ * NULL.  Allocates small device scratch for reductions (< 1 MiB) and, when
+ * desc->solid is given, a link table of 4 bytes per node built from the solid
+ * mask and the walls by a kernel enqueued on `stream` (the mask must be ready
+ * when that kernel runs; it is not referenced afterwards).  *out is set to NULL
+ * on error. */
 int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream);
 
 /* Release the context and its scratch (synchronises its stream). NULL is a no-op. */
@@ -150,6 +155,11 @@ int clbm_moments(clbm_ctx *ctx, const void *state, double *rho, double *u, doubl
 /* Pre-collision populations f(x, t) of a state, as device FP64 [27][N] in
  * Eq. (1) order (f itself, not the deviation).  Solid nodes get 0. */
 int clbm_get_populations(clbm_ctx *ctx, const void *state, double *f);
+
+/* Pre-collision populations of selected nodes: out (device FP64 [27][count])
+ * gets f_i at node nodes[k] (device int32 [count], node ids as above) in
+ * column k.  Solid nodes give 0; ids outside [0, N) give NaN.  count >= 0. */
+int clbm_sample_populations(clbm_ctx *ctx, const void *state, const int32_t *nodes, int32_t count, double *out);
 
 /* Inverse of clbm_get_populations: writes into `state` the buffer whose
  * pre-collision populations are f (device FP64 [27][N]); values are rounded to

@@ -75,6 +75,7 @@ def load_library(path: str = LIB_PATH):
         "clbm_moments": ([vp, vp, vp, vp, dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "clbm_get_populations": ([vp, vp, vp], ctypes.c_int),
         "clbm_set_populations": ([vp, vp, vp], ctypes.c_int),
+        "clbm_sample_populations": ([vp, vp, vp, i32, vp], ctypes.c_int),
         "clbm_adjoint_step": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "clbm_loss_seed": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
     }
@@ -175,6 +176,10 @@ class Context:
 
     def set_populations(self, f, state):
         self._call("clbm_set_populations", _ptr(f), _ptr(state))
+
+    def sample_populations(self, state, nodes, out):
+        self._call("clbm_sample_populations", _ptr(state), _ptr(nodes), ctypes.c_int32(int(nodes.numel())),
+                   _ptr(out))
 
     def adjoint_step(self, state_t, lam_next, lam_out, dJdF=None, dJds=None):
         self._call("clbm_adjoint_step", _ptr(state_t), _ptr(lam_next), _ptr(lam_out), _ptr(dJdF), _ptr(dJds))
@@ -299,6 +304,14 @@ class Lattice:
     def set_populations(self, f):
         ft = _dev_tensor(f, torch.float64, self.device, (27,) + self.shape)
         self.ctx.set_populations(ft, self.state)
+
+    def sample(self, xyz) -> np.ndarray:
+        """Pre-collision populations (27, k) f64 at the nodes xyz = [(x, y, z), ...]."""
+        nx, ny, _ = self.dims
+        ids = torch.tensor([x + nx * (y + ny * z) for x, y, z in xyz], dtype=torch.int32, device=self.device)
+        out = torch.empty((27, len(xyz)), dtype=torch.float64, device=self.device)
+        self.ctx.sample_populations(self.state, ids, out)
+        return out.cpu().numpy()
 
     def close(self):
         self.ctx.close()

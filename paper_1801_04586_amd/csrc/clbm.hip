@@ -29,6 +29,7 @@ struct clbm_ctx {
     size_t nodes;
     double *partials;  // [kMaxBlocks][kPartialStride]
     double *scal;      // [16] reduction results
+    uint32_t *links;   // [N] link table (k_links) when the lattice has solid nodes, else NULL
     char err[512];
 };
 
@@ -117,7 +118,7 @@ struct V {
 template <typename S, typename F>
 int dispatch_flags(const clbm_ctx *c, F &&f)
 {
-    const bool solid = c->d.solid != nullptr;
+    const bool solid = c->links != nullptr;
     const bool check = solid || c->d.wall[0] || c->d.wall[1] || c->d.wall[2];
     const bool field = c->d.force != nullptr;
     if (solid) return field ? f(V<S, true, true, true>{}) : f(V<S, true, true, false>{});
@@ -150,7 +151,7 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
         using S = typename Vt::Store;
         using R = typename Vt::R;
         hipLaunchKernelGGL((k_step<S, Vt::check, Vt::solid, Vt::field>), dim3(node_blocks(c)), dim3(kBlock), 0,
-                           c->stream, static_cast<const S *>(src), static_cast<S *>(dst), c->geom, c->d.solid,
+                           c->stream, static_cast<const S *>(src), static_cast<S *>(dst), c->geom, c->links,
                            static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
         return check_launch(c, "step kernel launch");
     });
@@ -211,6 +212,22 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
         delete c;
         return rc;
     }
+    c->links = nullptr;
+    if (desc->solid) {
+        e = hipMalloc(&c->links, sizeof(uint32_t) * c->nodes);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_links, dim3(node_blocks(c)), dim3(kBlock), 0, c->stream, c->geom, desc->solid, c->links);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) {
+            rc = hip_fail(nullptr, e, "link table");
+            if (c->links) (void)hipFree(c->links);
+            (void)hipFree(c->partials);
+            (void)hipFree(c->scal);
+            delete c;
+            return rc;
+        }
+    }
     *out = c;
     return CLBM_OK;
 }
@@ -223,6 +240,7 @@ int clbm_destroy(clbm_ctx *ctx)
     if (e != hipSuccess) rc = hip_fail(nullptr, e, "hipStreamSynchronize");
     (void)hipFree(ctx->partials);
     (void)hipFree(ctx->scal);
+    if (ctx->links) (void)hipFree(ctx->links);
     delete ctx;
     return rc;
 }
@@ -269,7 +287,7 @@ int clbm_init(clbm_ctx *ctx, void *state, const double *rho0, const double *u0)
         using Vt = decltype(v);
         using S = typename Vt::Store;
         hipLaunchKernelGGL((k_init<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0, ctx->stream,
-                           static_cast<S *>(state), ctx->geom, ctx->d.solid, rho0, u0);
+                           static_cast<S *>(state), ctx->geom, ctx->links, rho0, u0);
         return check_launch(ctx, "init kernel launch");
     });
 }
@@ -328,7 +346,7 @@ int clbm_moments(clbm_ctx *ctx, const void *state, double *rho, double *u, doubl
         using S = typename Vt::Store;
         using R = typename Vt::R;
         hipLaunchKernelGGL((k_moments<S, Vt::check, Vt::solid, Vt::field>), dim3(nb), dim3(kBlock), 0, ctx->stream,
-                           static_cast<const S *>(state), ctx->geom, ctx->d.solid, static_cast<const R *>(ctx->d.force),
+                           static_cast<const S *>(state), ctx->geom, ctx->links, static_cast<const R *>(ctx->d.force),
                            make_forcing<R>(ctx->d), rho, u, ctx->partials);
         return check_launch(ctx, "moments kernel launch");
     });
@@ -360,8 +378,26 @@ int clbm_get_populations(clbm_ctx *ctx, const void *state, double *f)
         using Vt = decltype(v);
         using S = typename Vt::Store;
         hipLaunchKernelGGL((k_get_populations<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
-                           ctx->stream, static_cast<const S *>(state), ctx->geom, ctx->d.solid, f);
+                           ctx->stream, static_cast<const S *>(state), ctx->geom, ctx->links, f);
         return check_launch(ctx, "get_populations kernel launch");
+    });
+}
+
+int clbm_sample_populations(clbm_ctx *ctx, const void *state, const int32_t *nodes, int32_t count, double *out)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (!state || !aligned(state) || count < 0) return fail(ctx, CLBM_EINVAL, "bad state or count");
+    if (count == 0) return CLBM_OK;
+    if (!nodes || !out || (reinterpret_cast<uintptr_t>(nodes) & 3u) || (reinterpret_cast<uintptr_t>(out) & 7u))
+        return fail(ctx, CLBM_EINVAL, "bad nodes/out buffers");
+    return dispatch(ctx, [&](auto v) {
+        using Vt = decltype(v);
+        using S = typename Vt::Store;
+        const unsigned blocks = static_cast<unsigned>((count + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_sample_populations<S, Vt::check, Vt::solid>), dim3(blocks), dim3(kBlock), 0,
+                           ctx->stream, static_cast<const S *>(state), ctx->geom, ctx->links, nodes,
+                           static_cast<uint32_t>(count), out);
+        return check_launch(ctx, "sample_populations kernel launch");
     });
 }
 
@@ -373,7 +409,7 @@ int clbm_set_populations(clbm_ctx *ctx, const double *f, void *state)
         using Vt = decltype(v);
         using S = typename Vt::Store;
         hipLaunchKernelGGL((k_set_populations<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
-                           ctx->stream, f, ctx->geom, ctx->d.solid, static_cast<S *>(state));
+                           ctx->stream, f, ctx->geom, ctx->links, static_cast<S *>(state));
         return check_launch(ctx, "set_populations kernel launch");
     });
 }
@@ -392,7 +428,7 @@ int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, 
         using S = typename Vt::Store;
         using R = typename Vt::R;
         hipLaunchKernelGGL((k_adjoint<S, Vt::check, Vt::solid, Vt::field>), dim3(nb), dim3(kBlock), 0, ctx->stream,
-                           static_cast<const S *>(state_t), ctx->geom, ctx->d.solid,
+                           static_cast<const S *>(state_t), ctx->geom, ctx->links,
                            static_cast<const R *>(ctx->d.force), make_forcing<R>(ctx->d), make_rates<R>(ctx->d.s),
                            static_cast<const R *>(lam_next), static_cast<R *>(lam_out), static_cast<R *>(dJdF),
                            ctx->partials);
@@ -417,7 +453,7 @@ int clbm_loss_seed(clbm_ctx *ctx, const void *state, const void *u_target, void 
         using S = typename Vt::Store;
         using R = typename Vt::R;
         hipLaunchKernelGGL((k_loss<S, Vt::check, Vt::solid, Vt::field>), dim3(nb), dim3(kBlock), 0, ctx->stream,
-                           static_cast<const S *>(state), ctx->geom, ctx->d.solid, static_cast<const R *>(ctx->d.force),
+                           static_cast<const S *>(state), ctx->geom, ctx->links, static_cast<const R *>(ctx->d.force),
                            make_forcing<R>(ctx->d), static_cast<const R *>(u_target), static_cast<R *>(lam_out),
                            static_cast<R *>(dJdF), ctx->partials);
         return check_launch(ctx, "loss kernel launch");

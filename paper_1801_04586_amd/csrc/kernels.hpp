@@ -130,22 +130,25 @@ __device__ __forceinline__ void neighbours(const Geom &g, uint32_t n, Nbr &nb)
 }
 
 // Is the link pulled by slot t open (neighbour x - e exists and is fluid)?  When
-// REV, the link towards x + e instead.
-template <int T, bool REV, bool SOLID>
-__device__ __forceinline__ bool link_open(const Nbr &nb, const uint8_t *__restrict__ solid, uint32_t &off)
+// REV, the link towards x + e instead.  Without solids the walls are tested from
+// the coordinates; with solids the node's link word lm (see k_links) holds the
+// answer for every slot, walls included.
+template <int T, bool REV, bool LINKS>
+__device__ __forceinline__ bool link_open(const Nbr &nb, uint32_t lm, uint32_t &off)
 {
     constexpr int a = REV ? 2 - sa(T) : sa(T), b = REV ? 2 - sb(T) : sb(T), c = REV ? 2 - sc(T) : sc(T);
     off = nb.zs[c] + nb.ys[b] + nb.xs[a];
-    bool ok = nb.vx[a] && nb.vy[b] && nb.vz[c];
-    if constexpr (SOLID) ok = ok && (solid[off] == 0);
-    return ok;
+    if constexpr (LINKS)
+        return (lm >> (REV ? 26 - T : T)) & 1u;
+    else
+        return nb.vx[a] && nb.vy[b] && nb.vz[c];
 }
 
 // Gather of Eq. (8): v[t] = population of slot t arriving at node n, as a real
 // (the stored value, deviation or not).  REV gathers along +e instead (adjoint).
 template <typename S, bool CHECK, bool SOLID, bool REV, typename R>
-__device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
-                                       const uint8_t *__restrict__ solid, R (&v)[27])
+__device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb, uint32_t lm,
+                                       R (&v)[27])
 {
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
@@ -155,7 +158,7 @@ __device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, ui
             v[t] = static_cast<R>(to_real(Pi[n]));
         } else {
             uint32_t off;
-            const bool ok = link_open<t, REV, SOLID>(nb, solid, off);
+            const bool ok = link_open<t, REV, SOLID>(nb, lm, off);
             if constexpr (CHECK) {
                 constexpr int ib = pop_of_slot(26 - t);
                 const S *p = ok ? (Pi + off) : (buf + static_cast<size_t>(ib) * N + n);
@@ -169,8 +172,8 @@ __device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, ui
 
 // Inverse of gather: write the value of slot t of node n where gather() reads it.
 template <typename S, bool CHECK, bool SOLID, typename R>
-__device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
-                                        const uint8_t *__restrict__ solid, const R (&v)[27])
+__device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb, uint32_t lm,
+                                        const R (&v)[27])
 {
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
@@ -181,7 +184,7 @@ __device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_
             Pi[n] = val;
         } else {
             uint32_t off;
-            const bool ok = link_open<t, false, SOLID>(nb, solid, off);
+            const bool ok = link_open<t, false, SOLID>(nb, lm, off);
             if constexpr (CHECK) {
                 constexpr int ib = pop_of_slot(26 - t);
                 S *p = ok ? (Pi + off) : (buf + static_cast<size_t>(ib) * N + n);
@@ -191,6 +194,25 @@ __device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_
             }
         }
     });
+}
+
+// Link table for lattices with solid nodes: word n has bit t set when the pull of
+// slot t into node n is open (the neighbour n - e exists and is fluid) and bit 13
+// (the rest population) set for every fluid node; solid nodes get 0.  One
+// coalesced 32-bit load per node then replaces 26 dependent mask loads.
+__global__ __launch_bounds__(kBlock) void k_links(Geom g, const uint8_t *__restrict__ solid, uint32_t *__restrict__ links)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    Nbr nb;
+    neighbours(g, n, nb);
+    uint32_t m = 0;
+    sfor<0, 27>([&](auto TT) {
+        constexpr int t = decltype(TT)::value;
+        uint32_t off;
+        if (link_open<t, false, false>(nb, 0u, off) && solid[off] == 0) m |= 1u << t;
+    });
+    links[n] = solid[n] ? 0u : (m | (1u << 13));
 }
 
 template <typename R>
@@ -213,25 +235,45 @@ __device__ __forceinline__ void force_at(const Forcing<R> &fo, const R *__restri
     }
 }
 
+// ------------------------------------------------------------------ XCD-aware block order
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each with
+// its own L2.  Remapping block b so that XCD k processes the k-th contiguous
+// eighth of the lattice keeps neighbouring tiles of a row on one XCD: the cache
+// lines that the x-shifted pulls share between adjacent tiles are then fetched
+// from HBM once instead of once per XCD.  The map is a bijection on [0, nb).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+    const uint32_t q = nb / 8, r = nb % 8, x = b % 8, k = b / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // ------------------------------------------------------------------ forward step
 // One fused time step on one node per thread (Steps 1-4 of Sec. II B).
+// A solid node reads nothing but still runs the arithmetic on the rest state and
+// stores its (never read) entries, so that every wavefront writes whole cache
+// lines: lanes that skipped their stores would leave partially written lines,
+// which cost far more memory time than the extra bytes.
 template <typename S, bool CHECK, bool SOLID, bool FIELD>
-__global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *__restrict__ dst, Geom g,
-                                                 const uint8_t *__restrict__ solid,
-                                                 const typename Traits<S>::R *__restrict__ field,
-                                                 Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
+__device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src, S *__restrict__ dst, const Geom &g,
+                                          const uint32_t *__restrict__ links,
+                                          const typename Traits<S>::R *__restrict__ field,
+                                          const Forcing<typename Traits<S>::R> &fo,
+                                          const Rates<typename Traits<S>::R> &rt)
 {
     using R = typename Traits<S>::R;
-    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
-    if constexpr (SOLID)
-        if (solid[n]) return;
+    uint32_t lm = 0;
+    if constexpr (SOLID) lm = links[n];
     Nbr nb;
     neighbours(g, n, nb);
     R v[27];
-    gather<S, CHECK, SOLID, false>(src, g.N, n, nb, solid, v);
-    if constexpr (!Traits<S>::kDev)
-        sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+    if (!SOLID || lm != 0u) {
+        gather<S, CHECK, SOLID, false>(src, g.N, n, nb, lm, v);
+        if constexpr (!Traits<S>::kDev)
+            sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+    } else {
+        sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });
+    }
 
     raw_moments(v);  // Eq. (4), (14): T = M d
     const R drho = v[slot(0, 0, 0)];
@@ -252,6 +294,16 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
         if constexpr (!Traits<S>::kDev) val += weight_of_slot<R>(t);
         dst[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = to_store<S>(val);
     });
+}
+
+template <typename S, bool CHECK, bool SOLID, bool FIELD>
+__global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *__restrict__ dst, Geom g,
+                                                 const uint32_t *__restrict__ links,
+                                                 const typename Traits<S>::R *__restrict__ field,
+                                                 Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
+{
+    step_node<S, CHECK, SOLID, FIELD>(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x, src, dst, g, links,
+                                      field, fo, rt);
 }
 
 // ------------------------------------------------------------------ block reductions (FP64, fixed order)
@@ -295,7 +347,7 @@ constexpr int kMomComp = 5;  // mass, momentum x/y/z, count of bad nodes
 
 template <typename S, bool CHECK, bool SOLID, bool FIELD>
 __global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, Geom g,
-                                                    const uint8_t *__restrict__ solid,
+                                                    const uint32_t *__restrict__ links,
                                                     const typename Traits<S>::R *__restrict__ field,
                                                     Forcing<typename Traits<S>::R> fo, double *__restrict__ rho_out,
                                                     double *__restrict__ u_out, double *__restrict__ partials)
@@ -303,7 +355,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, G
     using R = typename Traits<S>::R;
     double acc[kMomComp] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.N; n += gridDim.x * kBlock) {
-        if (SOLID && solid[n]) {
+        const uint32_t lm = SOLID ? links[n] : 0u;
+        if (SOLID && lm == 0u) {
             if (rho_out) rho_out[n] = 0.0;
             if (u_out) u_out[n] = u_out[g.N + n] = u_out[2 * static_cast<size_t>(g.N) + n] = 0.0;
             continue;
@@ -311,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, G
         Nbr nb;
         neighbours(g, n, nb);
         double v[27];
-        gather<S, CHECK, SOLID, false>(src, g.N, n, nb, solid, v);
+        gather<S, CHECK, SOLID, false>(src, g.N, n, nb, lm, v);
         if constexpr (!Traits<S>::kDev)
             sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<double>(decltype(T)::value); });
         raw_moments(v);
@@ -341,19 +394,20 @@ __global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, G
 // ------------------------------------------------------------------ populations in/out, initial state
 template <typename S, bool CHECK, bool SOLID>
 __global__ __launch_bounds__(kBlock) void k_get_populations(const S *__restrict__ src, Geom g,
-                                                            const uint8_t *__restrict__ solid,
+                                                            const uint32_t *__restrict__ links,
                                                             double *__restrict__ f)
 {
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
-    if (SOLID && solid[n]) {
+    const uint32_t lm = SOLID ? links[n] : 0u;
+    if (SOLID && lm == 0u) {
         for (int i = 0; i < 27; ++i) f[static_cast<size_t>(i) * g.N + n] = 0.0;
         return;
     }
     Nbr nb;
     neighbours(g, n, nb);
     double v[27];
-    gather<S, CHECK, SOLID, false>(src, g.N, n, nb, solid, v);
+    gather<S, CHECK, SOLID, false>(src, g.N, n, nb, lm, v);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         double val = v[t];
@@ -362,13 +416,43 @@ __global__ __launch_bounds__(kBlock) void k_get_populations(const S *__restrict_
     });
 }
 
+// Pre-collision populations of `count` listed nodes: out[i][k] for node nodes[k].
+template <typename S, bool CHECK, bool SOLID>
+__global__ __launch_bounds__(kBlock) void k_sample_populations(const S *__restrict__ src, Geom g,
+                                                               const uint32_t *__restrict__ links,
+                                                               const int32_t *__restrict__ nodes, uint32_t count,
+                                                               double *__restrict__ out)
+{
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= count) return;
+    const int32_t id = nodes[k];
+    const bool valid = id >= 0 && static_cast<uint32_t>(id) < g.N;
+    const uint32_t n = valid ? static_cast<uint32_t>(id) : 0u;
+    const uint32_t lm = SOLID ? links[n] : 0u;
+    if (!valid || (SOLID && lm == 0u)) {
+        for (int i = 0; i < 27; ++i) out[static_cast<size_t>(i) * count + k] = valid ? 0.0 : NAN;
+        return;
+    }
+    Nbr nb;
+    neighbours(g, n, nb);
+    double v[27];
+    gather<S, CHECK, SOLID, false>(src, g.N, n, nb, lm, v);
+    sfor<0, 27>([&](auto TT) {
+        constexpr int t = decltype(TT)::value;
+        double val = v[t];
+        if constexpr (Traits<S>::kDev) val += weight_of_slot<double>(t);
+        out[static_cast<size_t>(pop_of_slot(t)) * count + k] = val;
+    });
+}
+
 template <typename S, bool CHECK, bool SOLID>
 __global__ __launch_bounds__(kBlock) void k_set_populations(const double *__restrict__ f, Geom g,
-                                                            const uint8_t *__restrict__ solid, S *__restrict__ dst)
+                                                            const uint32_t *__restrict__ links, S *__restrict__ dst)
 {
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
-    if (SOLID && solid[n]) return;
+    const uint32_t lm = SOLID ? links[n] : 0u;
+    if (SOLID && lm == 0u) return;
     Nbr nb;
     neighbours(g, n, nb);
     double v[27];
@@ -378,18 +462,19 @@ __global__ __launch_bounds__(kBlock) void k_set_populations(const double *__rest
         if constexpr (Traits<S>::kDev) val -= weight_of_slot<double>(t);
         v[t] = val;
     });
-    scatter<S, CHECK, SOLID>(dst, g.N, n, nb, solid, v);
+    scatter<S, CHECK, SOLID>(dst, g.N, n, nb, lm, v);
 }
 
 // f = f_eq(rho0, u0): the generalized equilibrium (NM)^-1 T_eq, computed in FP64
 // as the reconstruction of T_eq - N(u) M w.
 template <typename S, bool CHECK, bool SOLID>
-__global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, const uint8_t *__restrict__ solid,
+__global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, const uint32_t *__restrict__ links,
                                                  const double *__restrict__ rho0, const double *__restrict__ u0)
 {
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
-    if (SOLID && solid[n]) return;
+    const uint32_t lm = SOLID ? links[n] : 0u;
+    if (SOLID && lm == 0u) return;
     Nbr nb;
     neighbours(g, n, nb);
     const double drho = rho0 ? rho0[n] - 1.0 : 0.0;
@@ -402,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, co
     reconstruct(v, ux, uy, uz);
     if constexpr (!Traits<S>::kDev)
         sfor<0, 27>([&](auto T) { v[decltype(T)::value] += weight_of_slot<double>(decltype(T)::value); });
-    scatter<S, CHECK, SOLID>(dst, g.N, n, nb, solid, v);
+    scatter<S, CHECK, SOLID>(dst, g.N, n, nb, lm, v);
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -411,67 +496,119 @@ __global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, co
 constexpr int kAdjRates = 8;
 
 // One adjoint step on one node per thread (grid-stride).  Recomputes the forward
-// collision from the state at t, gathers lambda(t+1) along +e (the transpose of
+// moments from the state at t, gathers lambda(t+1) along +e (the transpose of
 // the pull), applies the transposed per-node Jacobian and writes lambda(t).
+//
+// Per-axis shifts satisfy N1(-u) = exp(u D) and N1(u) = exp(-u D) with the
+// lowering operator (D v)_m = m v_{m-1}, which commutes with both.  Hence the
+// velocity derivatives of the two shifts, contracted with the adjoint, are
+//   from N(-u):  abar~*^T D_a T~*,     from N(u):  -abar~^T D_a T~,
+// in terms of the central moments before (T~) and after (T~*) the collision and
+// their adjoints.  Only T~ and one adjoint vector are kept live; T~* is re-formed
+// slot by slot from T~.
 template <typename S, bool CHECK, bool SOLID, bool FIELD>
-__global__ __launch_bounds__(kBlock) void k_adjoint(const S *__restrict__ state, Geom g,
-                                                    const uint8_t *__restrict__ solid,
-                                                    const typename Traits<S>::R *__restrict__ field,
-                                                    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt,
-                                                    const typename Traits<S>::R *__restrict__ lam_next,
-                                                    typename Traits<S>::R *__restrict__ lam_out,
-                                                    typename Traits<S>::R *__restrict__ dJdF,
-                                                    double *__restrict__ partials)
+__device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const Geom &g,
+                                              const uint32_t *__restrict__ links,
+                                              const typename Traits<S>::R *__restrict__ field,
+                                              const Forcing<typename Traits<S>::R> &fo,
+                                              const Rates<typename Traits<S>::R> &rt,
+                                              const typename Traits<S>::R *__restrict__ lam_next,
+                                              typename Traits<S>::R *__restrict__ lam_out,
+                                              typename Traits<S>::R *__restrict__ dJdF, double *__restrict__ partials)
 {
     using R = typename Traits<S>::R;
     constexpr R cs2 = R(1.0 / 3.0), cs4 = R(1.0 / 9.0);
     double gs[kAdjRates] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.N; n += gridDim.x * kBlock) {
-        if (SOLID && solid[n]) {
-            for (int i = 0; i < 27; ++i) lam_out[static_cast<size_t>(i) * g.N + n] = R(0);
-            continue;
+        // A solid node reads no state or adjoint: with zero inputs every output below is
+        // exactly zero (lambda = 0, no force or rate contribution), and its stores keep
+        // the wavefront's cache lines whole.
+        uint32_t lm = 0;
+        if constexpr (SOLID) lm = links[n];
+        const bool fluid = !SOLID || lm != 0u;
+        // accumulated force gradient of this node, loaded up front with the other operands
+        R gFx = R(0), gFy = R(0), gFz = R(0);
+        if (dJdF) {
+            gFx = dJdF[n];
+            gFy = dJdF[g.N + n];
+            gFz = dJdF[2 * static_cast<size_t>(g.N) + n];
         }
         Nbr nb;
         neighbours(g, n, nb);
-        // ---- forward recomputation
+        // ---- forward recomputation: T~ (full central moments) at this node
         R tt[27];
-        gather<S, CHECK, SOLID, false>(state, g.N, n, nb, solid, tt);
-        if constexpr (!Traits<S>::kDev)
-            sfor<0, 27>([&](auto T) { tt[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+        if (fluid) {
+            gather<S, CHECK, SOLID, false>(state, g.N, n, nb, lm, tt);
+            if constexpr (!Traits<S>::kDev)
+                sfor<0, 27>([&](auto T) { tt[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+        } else {
+            sfor<0, 27>([&](auto T) { tt[decltype(T)::value] = R(0); });
+        }
         raw_moments(tt);
-        const R drho = tt[slot(0, 0, 0)];
-        const R rho = R(1) + drho;
+        const R rho = R(1) + tt[slot(0, 0, 0)];
         const R inv_rho = R(1) / rho;
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
         const R ux = (tt[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho;
         const R uy = (tt[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho;
         const R uz = (tt[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho;
-        central_shift(tt, ux, uy, uz);  // tt = central moments of d
-        const AxisU<R> X(ux), Y(uy), Z(uz);
-        R ts[27];  // post-collision raw moments T* (full, not deviations)
-        sfor<0, 27>([&](auto T) { ts[decltype(T)::value] = tt[decltype(T)::value]; });
-        collide(ts, drho, X, Y, Z, Fx, Fy, Fz, rt);
-        central_unshift(ts, ux, uy, uz);
-        sfor<0, 27>([&](auto T) {
-            constexpr int t = decltype(T)::value;
-            constexpr R E = R(e_of(sa(t)) * e_of(sb(t)) * e_of(sc(t)));
-            if constexpr (E != R(0)) ts[t] += E;
-        });
-        // full central moments T~ = tt + c (x) c (x) c
-        sfor<0, 27>([&](auto T) {
-            constexpr int t = decltype(T)::value;
-            tt[t] += cw_term<sa(t), sb(t), sc(t)>(X, Y, Z);
-        });
+        central_shift(tt, ux, uy, uz);
+        {
+            const AxisU<R> X(ux), Y(uy), Z(uz);
+            sfor<0, 27>([&](auto T) {
+                constexpr int t = decltype(T)::value;
+                tt[t] += cw_term<sa(t), sb(t), sc(t)>(X, Y, Z);
+            });
+        }
+        // non-equilibrium part of the normal-stress block (Eq. (13)), shared by T~* and the rates
+        constexpr int ix = slot(2, 0, 0), iy = slot(0, 2, 0), iz = slot(0, 0, 2);
+        const R rx = fma(rho, cs2, -tt[ix]), ry = fma(rho, cs2, -tt[iy]), rz = fma(rho, cs2, -tt[iz]);
+        const R rsum = rx + ry + rz;
 
-        // ---- adjoint: a = dJ/df*(x), gathered along +e
+        // ---- adjoint of f*: gather lambda(t+1) along +e, then through M^-1 and N(-u)
         R a[27];
-        gather<R, CHECK, SOLID, true>(lam_next, g.N, n, nb, solid, a);
-        reconstruct_raw_T(a);  // a = M^-T a  (adjoint of T*)
-        R ubx = lowered_dot<0>(a, ts), uby = lowered_dot<1>(a, ts), ubz = lowered_dot<2>(a, ts);
+        if (fluid)
+            gather<R, CHECK, SOLID, true>(lam_next, g.N, n, nb, lm, a);
+        else
+            sfor<0, 27>([&](auto T) { a[decltype(T)::value] = R(0); });
+        reconstruct_raw_T(a);
         unshift_T(a, ux, uy, uz);  // a = adjoint of T~*
 
-        // collision backward
+        // u-derivative of N(-u): sum_b T~*(b) * m * a(b + e_axis) over the slots b below each axis
+        R ubx = R(0), uby = R(0), ubz = R(0);
+        sfor<0, 27>([&](auto T) {
+            constexpr int b = decltype(T)::value;
+            constexpr int m = sa(b), nn = sb(b), p = sc(b);
+            if constexpr (m < 2 || nn < 2 || p < 2) {
+                constexpr int ones = (m == 1) + (nn == 1) + (p == 1);
+                constexpr int order = m + nn + p;
+                R ts;  // post-collision central moment T~*(b), Eq. (5)
+                if constexpr (order == 0) {
+                    ts = rho;
+                } else if constexpr (order == 1) {
+                    ts = R(0.5) * (m == 1 ? Fx : (nn == 1 ? Fy : Fz));
+                } else if constexpr (order == 2 && ones == 0) {
+                    const R r = b == ix ? rx : (b == iy ? ry : rz);
+                    ts = tt[b] + fma(rt.s[R_S2], r, rt.sm * rsum);
+                } else {
+                    constexpr int k = rate_of(m, nn, p);
+                    constexpr R E = R(e_of(m) * e_of(nn) * e_of(p));
+                    R r = -tt[b];
+                    if constexpr (ones == 0) r = fma(rho, E, r);
+                    ts = fma(rt.s[k], r, tt[b]);
+                    if constexpr (ones == 1) {
+                        constexpr R cf = order == 3 ? cs2 : cs4;
+                        const R Fa = m == 1 ? Fx : (nn == 1 ? Fy : Fz);
+                        ts = fma(rt.hs[k] * cf, Fa, ts);
+                    }
+                }
+                if constexpr (m < 2) ubx = fma(R(m + 1) * a[b + 9], ts, ubx);
+                if constexpr (nn < 2) uby = fma(R(nn + 1) * a[b + 3], ts, uby);
+                if constexpr (p < 2) ubz = fma(R(p + 1) * a[b + 1], ts, ubz);
+            }
+        });
+
+        // ---- collision backward: a <- (I - S) a on non-conserved slots, conserved slots feed rho and F
         R rhob = a[slot(0, 0, 0)];
         R Fbx = R(0.5) * a[slot(1, 0, 0)], Fby = R(0.5) * a[slot(0, 1, 0)], Fbz = R(0.5) * a[slot(0, 0, 1)];
         a[slot(0, 0, 0)] = R(0);
@@ -487,17 +624,16 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const S *__restrict__ state,
                 constexpr int k = rate_of(m, nn, p);
                 constexpr R E = R(e_of(m) * e_of(nn) * e_of(p));
                 const R y = a[t];
-                // R = rho E - T~ - C/2
-                R r = -tt[t];
+                R r = -tt[t];  // rho E - T~ - C/2
                 if constexpr (ones == 0) r = fma(rho, E, r);
                 if constexpr (ones == 1) {
                     constexpr R cf = order == 3 ? cs2 : cs4;
                     const R Fa = m == 1 ? Fx : (nn == 1 ? Fy : Fz);
                     r = fma(R(-0.5) * cf, Fa, r);
-                    const R g = rt.hs[k] * cf * y;
-                    if constexpr (m == 1) Fbx += g;
-                    else if constexpr (nn == 1) Fby += g;
-                    else Fbz += g;
+                    const R gF = rt.hs[k] * cf * y;
+                    if constexpr (m == 1) Fbx += gF;
+                    else if constexpr (nn == 1) Fby += gF;
+                    else Fbz += gF;
                 }
                 gs[k - 2] += static_cast<double>(y * r);
                 if constexpr (ones == 0) rhob = fma(rt.s[k] * E, y, rhob);
@@ -505,10 +641,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const S *__restrict__ state,
             }
         });
         {
-            constexpr int ix = slot(2, 0, 0), iy = slot(0, 2, 0), iz = slot(0, 0, 2);
             const R yx = a[ix], yy = a[iy], yz = a[iz];
-            const R rx = fma(rho, cs2, -tt[ix]), ry = fma(rho, cs2, -tt[iy]), rz = fma(rho, cs2, -tt[iz]);
-            const R ysum = yx + yy + yz, rsum = rx + ry + rz;
+            const R ysum = yx + yy + yz;
             const R tr = rt.sm * ysum;
             const R sx = fma(rt.s[R_S2], yx, tr), sy = fma(rt.s[R_S2], yy, tr), sz = fma(rt.s[R_S2], yz, tr);
             a[ix] = yx - sx;
@@ -519,10 +653,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const S *__restrict__ state,
             gs[R_S2 - 2] += static_cast<double>(yx * rx + yy * ry + yz * rz) - third;
             gs[R_S2B - 2] += third;
         }
+        // u-derivative of N(u), then back through N(u) and M
         ubx -= lowered_dot<0>(a, tt);
         uby -= lowered_dot<1>(a, tt);
         ubz -= lowered_dot<2>(a, tt);
-        shift_T(a, ux, uy, uz);  // a = adjoint of T (raw moments)
+        shift_T(a, ux, uy, uz);
         // u = (j + F/2) / rho
         a[slot(1, 0, 0)] += ubx * inv_rho;
         a[slot(0, 1, 0)] += uby * inv_rho;
@@ -539,17 +674,32 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const S *__restrict__ state,
             lam_out[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = a[t];
         });
         if (dJdF) {
-            dJdF[n] += Fbx;
-            dJdF[g.N + n] += Fby;
-            dJdF[2 * static_cast<size_t>(g.N) + n] += Fbz;
+            dJdF[n] = gFx + Fbx;
+            dJdF[g.N + n] = gFy + Fby;
+            dJdF[2 * static_cast<size_t>(g.N) + n] = gFz + Fbz;
         }
     }
     block_reduce_store<kAdjRates>(gs, partials + static_cast<size_t>(blockIdx.x) * kAdjRates);
 }
 
-// Loss J = 1/2 sum_fluid |u - u_t|^2 and its seed lambda = dJ/df; adds dJ/dF (direct).
 template <typename S, bool CHECK, bool SOLID, bool FIELD>
-__global__ __launch_bounds__(kBlock) void k_loss(const S *__restrict__ state, Geom g, const uint8_t *__restrict__ solid,
+__global__ __launch_bounds__(kBlock) void k_adjoint(const S *__restrict__ state, Geom g,
+                                                    const uint32_t *__restrict__ links,
+                                                    const typename Traits<S>::R *__restrict__ field,
+                                                    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt,
+                                                    const typename Traits<S>::R *__restrict__ lam_next,
+                                                    typename Traits<S>::R *__restrict__ lam_out,
+                                                    typename Traits<S>::R *__restrict__ dJdF,
+                                                    double *__restrict__ partials)
+{
+    adjoint_nodes<S, CHECK, SOLID, FIELD>(state, g, links, field, fo, rt, lam_next, lam_out, dJdF, partials);
+}
+
+// Loss J = 1/2 sum_fluid |u - u_t|^2 and its seed lambda = dJ/df; adds dJ/dF (direct).
+// Solid nodes read no state and contribute nothing, but store zeros (whole lines).
+template <typename S, bool CHECK, bool SOLID, bool FIELD>
+__global__ __launch_bounds__(kBlock) void k_loss(const S *__restrict__ state, Geom g,
+                                                 const uint32_t *__restrict__ links,
                                                  const typename Traits<S>::R *__restrict__ field,
                                                  Forcing<typename Traits<S>::R> fo,
                                                  const typename Traits<S>::R *__restrict__ u_target,
@@ -559,16 +709,19 @@ __global__ __launch_bounds__(kBlock) void k_loss(const S *__restrict__ state, Ge
     using R = typename Traits<S>::R;
     double acc[1] = {0.0};
     for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.N; n += gridDim.x * kBlock) {
-        if (SOLID && solid[n]) {
-            for (int i = 0; i < 27; ++i) lam_out[static_cast<size_t>(i) * g.N + n] = R(0);
-            continue;
-        }
+        uint32_t lm = 0;
+        if constexpr (SOLID) lm = links[n];
+        const bool fluid = !SOLID || lm != 0u;
         Nbr nb;
         neighbours(g, n, nb);
         R v[27];
-        gather<S, CHECK, SOLID, false>(state, g.N, n, nb, solid, v);
-        if constexpr (!Traits<S>::kDev)
-            sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+        if (fluid) {
+            gather<S, CHECK, SOLID, false>(state, g.N, n, nb, lm, v);
+            if constexpr (!Traits<S>::kDev)
+                sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+        } else {
+            sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });
+        }
         raw_moments(v);
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
@@ -576,7 +729,9 @@ __global__ __launch_bounds__(kBlock) void k_loss(const S *__restrict__ state, Ge
         const R ux = (v[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho;
         const R uy = (v[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho;
         const R uz = (v[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho;
-        const R dx = ux - u_target[n], dy = uy - u_target[g.N + n], dz = uz - u_target[2 * static_cast<size_t>(g.N) + n];
+        const R dx = fluid ? ux - u_target[n] : R(0);
+        const R dy = fluid ? uy - u_target[g.N + n] : R(0);
+        const R dz = fluid ? uz - u_target[2 * static_cast<size_t>(g.N) + n] : R(0);
         acc[0] += 0.5 * (static_cast<double>(dx) * dx + static_cast<double>(dy) * dy + static_cast<double>(dz) * dz);
         // dJ/df_i = sum_a d_a (e_ia - u_a) / rho
         const R bx = dx * inv_rho, by = dy * inv_rho, bz = dz * inv_rho;

@@ -1,0 +1,212 @@
+"""Adjoint kernels (through the C ABI) against the FP64 CPU oracle's exact
+discrete adjoint, central finite differences, and checkpoint invariance."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+RATES = np.array([1.0, 1.0, 1.55, 1.2, 1.3, 0.9, 1.1, 1.25, 0.95, 1.05])
+
+
+def _lattice(dims, walls, storage, rates=RATES, force=(0.0, 0.0, 0.0), field=None, solid=None):
+    from paper_1801_04586_amd import Lattice
+
+    return Lattice(dims, walls, storage, rates, force=force, force_field=field, solid=solid)
+
+
+def _case(dims, walls, seed, solid_frac):
+    g = oracle.Geometry(dims, walls)
+    rho0, u0 = workloads.random_state_fields(dims, seed, du=0.04, drho=0.01)
+    f0 = oracle.init(g, rho0, u0) + workloads.random_populations_perturbation(dims, seed + 1, 5e-4)
+    field = workloads.gaussian_force(dims, 1e-4, seed + 2)
+    solid = workloads.random_solids(dims, solid_frac, seed + 3) if solid_frac else None
+    return g, f0, field, solid
+
+
+@pytest.mark.parametrize("walls,solid_frac", [((0, 0, 0), 0.0), ((0, 1, 0), 0.0), ((1, 1, 1), 0.2)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-5)])
+def test_adjoint_step_matches_oracle(walls, solid_frac, storage, tol):
+    dims = (7, 6, 5)
+    g, f0, field, solid = _case(dims, walls, 11, solid_frac)
+    force = (1e-5, -2e-5, 5e-6)
+    lat = _lattice(dims, walls, storage, force=force, field=field, solid=solid)
+    lat.set_populations(torch.from_numpy(f0))
+    f_state = lat.populations().cpu().numpy()  # what the kernel sees (rounded to storage)
+    lam_next = np.random.default_rng(5).normal(0, 1, (27,) + g.shape)
+    real = torch.float64 if storage == "f64" else torch.float32
+    ln = torch.from_numpy(lam_next).to("cuda", real).contiguous()
+    lam_next_used = ln.double().cpu().numpy()
+    lo = torch.empty_like(ln)
+    gF = torch.zeros((3,) + g.shape, dtype=real, device="cuda")
+    gs = torch.zeros(10, dtype=torch.float64, device="cuda")
+    lat.ctx.adjoint_step(lat.state, ln, lo, gF, gs)
+    field_used = lat.force_field.double().cpu().numpy()
+    ref_lam, ref_gF, ref_gs = oracle.adjoint_step(g, f_state, lam_next_used, RATES, force=force,
+                                                  force_field=field_used, solid=solid)
+    fl = np.ones(g.shape, bool) if solid is None else solid == 0
+    got = lo.double().cpu().numpy()
+    scale = np.max(np.abs(ref_lam[:, fl]))
+    assert np.max(np.abs(got[:, fl] - ref_lam[:, fl])) <= tol * scale
+    gFg = gF.double().cpu().numpy()
+    assert np.max(np.abs(gFg[:, fl] - ref_gF[:, fl])) <= tol * np.max(np.abs(ref_gF[:, fl]))
+    gsg = gs.cpu().numpy()
+    assert gsg[0] == 0.0 and gsg[1] == 0.0
+    assert np.max(np.abs(gsg[2:] - ref_gs[2:])) <= tol * np.max(np.abs(ref_gs[2:])) * 10
+    if solid is not None:
+        assert np.all(got[:, ~fl] == 0.0)
+    lat.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-13), ("f32", 1e-6)])
+def test_loss_seed_matches_oracle(storage, tol):
+    dims, walls = (9, 8, 4), (0, 1, 0)
+    g, f0, field, solid = _case(dims, walls, 21, 0.15)
+    ut = workloads.uniform_random_velocity(dims, 0.03, 22)
+    lat = _lattice(dims, walls, storage, force=(3e-6, 0, 0), field=field, solid=solid)
+    lat.set_populations(torch.from_numpy(f0))
+    f_state = lat.populations().cpu().numpy()
+    real = lat.real
+    utd = torch.from_numpy(ut).to("cuda", real).contiguous()
+    lam = torch.empty((27,) + g.shape, dtype=real, device="cuda")
+    gF = torch.zeros((3,) + g.shape, dtype=real, device="cuda")
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lat.ctx.loss_seed(lat.state, utd, lam, gF, J)
+    Jr, lr, gFr = oracle.loss_seed(g, f_state, utd.double().cpu().numpy(), force=(3e-6, 0, 0),
+                                   force_field=lat.force_field.double().cpu().numpy(), solid=solid)
+    assert abs(J.item() - Jr) <= tol * Jr
+    fl = solid == 0
+    got = lam.double().cpu().numpy()
+    assert np.max(np.abs(got[:, fl] - lr[:, fl])) <= tol * np.max(np.abs(lr))
+    assert np.max(np.abs(gF.double().cpu().numpy()[:, fl] - gFr[:, fl])) <= tol * np.max(np.abs(gFr))
+    lat.close()
+
+
+def _channel(dims, storage, seed=workloads.SEED):
+    """The adjoint channel case: walls in y, nu = 0.05, learnable force N(0, 1e-12), parabolic target."""
+    from paper_1801_04586_amd import Lattice
+
+    walls = (0, 1, 0)
+    rates = workloads.rates(0.05)
+    F = workloads.gaussian_force(dims, 1e-6, seed)
+    ut = workloads.channel_target(dims, walls, 1e-4)
+    lat = Lattice(dims, walls, storage, rates, force_field=F)
+    lat.init()
+    state0 = lat.state.clone()
+    return lat, state0, F, ut, rates
+
+
+def test_checkpoint_and_recompute_are_bitwise_equal_to_storing_every_state():
+    from paper_1801_04586_amd.adjoint import flow_loss
+
+    dims = (12, 10, 8)
+    outs = []
+    for K in (1, 7, 20, 45):
+        lat, state0, F, ut, rates = _channel(dims, "f32")
+        Ft = torch.from_numpy(F).float().cuda().requires_grad_(True)
+        st = torch.from_numpy(rates).requires_grad_(True)
+        J = flow_loss(Ft, st, lat, state0, torch.from_numpy(ut).float().cuda(), 45, K)
+        J.backward()
+        outs.append((J.item(), Ft.grad.clone(), st.grad.clone()))
+        lat.close()
+    for J, gF, gs in outs[1:]:
+        assert J == outs[0][0]
+        assert torch.equal(gF, outs[0][1])
+        assert torch.equal(gs, outs[0][2])
+
+
+def test_flow_loss_gradient_matches_central_differences_fp64():
+    """dJ/dF (random direction) and dJ/ds_k against central differences, eps = 1e-4 relative, FP64."""
+    from paper_1801_04586_amd.adjoint import flow_loss
+
+    dims, T = (10, 12, 6), 40
+    lat, state0, F, ut, rates = _channel(dims, "f64")
+    utd = torch.from_numpy(ut).cuda()
+    Ft = torch.from_numpy(F).cuda().requires_grad_(True)
+    st = torch.from_numpy(rates.copy()).requires_grad_(True)
+    J = flow_loss(Ft, st, lat, state0, utd, T, 8)
+    J.backward()
+    gF, gs = Ft.grad.cpu().numpy(), st.grad.numpy()
+
+    def Jof(Fa, sa):
+        with torch.no_grad():
+            return flow_loss(torch.from_numpy(Fa).cuda(), torch.from_numpy(sa), lat, state0, utd, T, 8).item()
+
+    v = np.random.default_rng(3).normal(0, 1, F.shape)
+    eps = 1e-4 * np.max(np.abs(F))
+    fd = (Jof(F + eps * v, rates) - Jof(F - eps * v, rates)) / (2 * eps)
+    assert abs(fd - np.sum(gF * v)) <= 1e-6 * abs(fd)
+    for k in (2, 3, 4, 6, 9):
+        sp, sm = rates.copy(), rates.copy()
+        h = 1e-4 * rates[k]
+        sp[k] += h
+        sm[k] -= h
+        fd = (Jof(F, sp) - Jof(F, sm)) / (2 * h)
+        # truncation of the O(h^2) difference dominates for derivatives far below the largest one
+        assert abs(fd - gs[k]) <= 1e-5 * abs(fd) + 1e-7 * np.max(np.abs(gs)), (k, fd, gs[k])
+    assert gs[0] == 0.0 and gs[1] == 0.0
+    lat.close()
+
+
+def test_fp32_adjoint_matches_fp64_cpu_adjoint_on_8cubed_channel():
+    """The adjoint channel case on an 8^3 subcase: FP32 GPU adjoint (T = 200, checkpoint every 20)
+    against the FP64 CPU oracle's exact adjoint of the same run."""
+    from paper_1801_04586_amd.adjoint import flow_loss
+
+    dims, T = (8, 8, 8), 200
+    lat, state0, F, ut, rates = _channel(dims, "f32")
+    Ft = torch.from_numpy(F).float().cuda().requires_grad_(True)
+    st = torch.from_numpy(rates.copy()).requires_grad_(True)
+    J = flow_loss(Ft, st, lat, state0, torch.from_numpy(ut).float().cuda(), T, 20)
+    J.backward()
+    g = oracle.Geometry(dims, (0, 1, 0))
+    f0 = oracle.init(g)
+    Jr, gFr, gsr, _ = oracle.loss_and_grads(g, f0, rates, T, ut, force_field=Ft.detach().double().cpu().numpy())
+    assert abs(J.item() - Jr) <= 1e-4 * Jr
+    gF = Ft.grad.double().cpu().numpy()
+    assert np.linalg.norm(gF - gFr) <= 1e-4 * np.linalg.norm(gFr)
+    gs = st.grad.numpy()
+    for k in range(2, 10):
+        assert abs(gs[k] - gsr[k]) <= 1e-4 * np.max(np.abs(gsr[2:])), (k, gs[k], gsr[k])
+    lat.close()
+
+
+def test_adjoint_on_full_channel_case_fp32_vs_fp64_differences():
+    """64^3 channel, T = 200, K = 20, FP32: directional derivative along a random force direction
+    against central differences of the same loss evaluated with FP64 storage (eps = 1e-4 relative)."""
+    from paper_1801_04586_amd.adjoint import flow_loss
+
+    dims, T = (64, 64, 64), 200
+    lat, state0, F, ut, rates = _channel(dims, "f32")
+    Ft = torch.from_numpy(F).float().cuda().requires_grad_(True)
+    st = torch.from_numpy(rates.copy()).requires_grad_(True)
+    J = flow_loss(Ft, st, lat, state0, torch.from_numpy(ut).float().cuda(), T, 20)
+    J.backward()
+    gF = Ft.grad.double().cpu().numpy()
+    gs = st.grad.numpy()
+    lat.close()
+    lat64, s64, _, _, _ = _channel(dims, "f64")
+    utd = torch.from_numpy(ut).cuda()
+    F32 = Ft.detach().double().cpu().numpy()  # the FP32-rounded field both sides use
+
+    def Jof(Fa, sa):
+        with torch.no_grad():
+            return flow_loss(torch.from_numpy(Fa).cuda(), torch.from_numpy(sa), lat64, s64, utd, T, 20).item()
+
+    v = np.random.default_rng(11).normal(0, 1, F.shape)
+    eps = 1e-4 * np.max(np.abs(F32))
+    fd = (Jof(F32 + eps * v, rates) - Jof(F32 - eps * v, rates)) / (2 * eps)
+    assert abs(fd - np.sum(gF * v)) <= 1e-3 * abs(fd)
+    k = 2
+    sp, sm = rates.copy(), rates.copy()
+    h = 1e-4 * rates[k]
+    sp[k] += h
+    sm[k] -= h
+    fd = (Jof(F32, sp) - Jof(F32, sm)) / (2 * h)
+    assert abs(fd - gs[k]) <= 1e-3 * abs(fd)
+    lat64.close()
