@@ -32,7 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD datasheet
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_step_f32_kolmogorov512.json")
+PMC_SINGLE = os.path.join(ROOT, "profiles", "pmc_k_step_f32_kolmogorov512.json")
+PMC_FUSED = os.path.join(ROOT, "profiles", "pmc_k_step2_f32_kolmogorov512.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_04586_amd", "csrc", f) for f in ("node.hpp", "kernels.hpp")]
 
 
@@ -56,6 +57,18 @@ def bytes_per_node(storage: str, field: bool, solid: bool) -> int:
     if solid:
         b += 1
     return b
+
+
+def pmc_traffic(path: str, size: int, fused: bool):
+    """HBM bytes per launch from a committed counter summary, if it was taken on
+    the current kernel source, lattice size and launch kind; else None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        pmc = json.load(fh)
+    if pmc.get("kernel_src_sha") == kernel_sha() and pmc.get("size") == size and pmc.get("fused") == fused:
+        return pmc.get("hbm_bytes_per_launch")
+    return None
 
 
 def trimmed_mean(xs):
@@ -132,6 +145,8 @@ def main():
     lat.init(None, u0_dev)
     lat.step(args.warmup)
     torch.cuda.synchronize()
+    fused = lat.uses_fused_pairs
+    launches = (args.steps // 2 + args.steps % 2) if fused else args.steps
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
@@ -139,13 +154,15 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    event_ms = ev0.elapsed_time(ev1)
+    kernel_ms = event_ms / launches
     ms_per_step = wall * 1e3 / args.steps
     mlups = nodes * args.steps / wall / 1e6
     bpn = bytes_per_node("f32", True, False)
-    achieved = bpn * nodes / (kernel_ms * 1e-3) / 1e9
-    log(f"[bench] f32: {ms_per_step:.3f} ms/step wall, {kernel_ms:.3f} ms/kernel, {mlups:.0f} MLUPS, "
-        f"{achieved:.0f} GB/s algorithmic")
+    # algorithmic bytes of the node updates done in the timed region, per unit of kernel time
+    achieved = bpn * nodes * args.steps / (event_ms * 1e-3) / 1e9
+    log(f"[bench] f32 ({'two fused steps per launch' if fused else 'one step per launch'}): {ms_per_step:.3f} "
+        f"ms/step wall, {kernel_ms:.3f} ms/launch, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic")
     _, _, tot, nbad = lat.moments(fields=False)
     if nbad:
         log(f"[bench] WARNING: {nbad} non-finite nodes")
@@ -165,12 +182,8 @@ def main():
             f"{2 * lat.state.numel() * 4 / (cms * 1e-3) / 1e9:.0f} GB/s read+write")
         del tmp
 
-    traffic = None
-    if os.path.exists(PMC_SUMMARY):
-        with open(PMC_SUMMARY) as fh:
-            pmc = json.load(fh)
-        if pmc.get("kernel_src_sha") == kernel_sha() and pmc.get("size") == L:
-            traffic = pmc.get("hbm_bytes_per_launch")
+    traffic = pmc_traffic(PMC_FUSED if fused else PMC_SINGLE, L, fused)
+    kname = "k_step2<float, force field> (two fused steps)" if fused else "k_step<float, periodic, force field>"
 
     result = {
         "metric": "MLUPS (FP32-storage fused D3Q27 cascaded-LBM step) and fraction of HBM roofline",
@@ -201,11 +214,22 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_step<float, periodic, force field>",
+            "kernel": kname,
             "kernel_ms": round(kernel_ms, 4),
-            "algorithmic_bytes_per_launch": bpn * nodes,
+            "node_updates_per_launch": nodes * (2 if fused else 1),
+            "algorithmic_bytes_per_launch": bpn * nodes * (2 if fused else 1),
         },
     }
+    if fused:
+        # the same lattice with one step per launch, for comparison
+        lat.set_fused_steps(False)
+        ms1 = time_steps(torch, lat, 10)
+        lat.set_fused_steps(True)
+        result["single_step_kernel"] = {
+            "mlups": round(nodes / (ms1 * 1e-3) / 1e6, 1), "kernel_ms": round(ms1, 4),
+            "frac": round(bpn * nodes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": pmc_traffic(PMC_SINGLE, L, False)}
+        log(f"[bench] f32 single steps: {result['single_step_kernel']}")
     if args.primary_only:
         print(json.dumps(result), flush=True)
         return
@@ -229,16 +253,23 @@ def main():
             b = bytes_per_node(storage, True, False)
             variants[f"kolmogorov_{L}_{storage}"] = {
                 "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4),
+                "launch": "two fused steps" if lv.uses_fused_pairs else "one step",
                 "bytes_per_node": b, "frac": round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            if lv.uses_fused_pairs:
+                lv.set_fused_steps(False)
+                ms1 = time_steps(torch, lv, 10)
+                lv.set_fused_steps(True)
+                variants[f"kolmogorov_{L}_{storage}"]["single_step_mlups"] = round(nodes / (ms1 * 1e-3) / 1e6, 1)
             log(f"[bench] {storage}: {ms:.3f} ms/step, {variants[f'kolmogorov_{L}_{storage}']}")
             lv.close()
             del lv
             torch.cuda.empty_cache()
-        variants[f"kolmogorov_{L}_f32"] = {"mlups": round(nodes / (kernel_ms * 1e-3) / 1e6, 1),
-                                           "kernel_ms": round(kernel_ms, 4), "bytes_per_node": bpn,
+        step_ms = event_ms / args.steps
+        variants[f"kolmogorov_{L}_f32"] = {"mlups": round(nodes / (step_ms * 1e-3) / 1e6, 1),
+                                           "ms_per_step": round(step_ms, 4), "bytes_per_node": bpn,
                                            "frac": round(achieved / HBM_PEAK_GBS, 4)}
         f64k = variants[f"kolmogorov_{L}_f64"]["kernel_ms"]
-        result["speedup_f32_over_f64"] = round(f64k / kernel_ms, 3)
+        result["speedup_f32_over_f64"] = round(f64k / step_ms, 3)
 
         # plain kernel on the 128^3 Taylor-Green case
         tdims = (128, 128, 128)

@@ -134,12 +134,25 @@ int clbm_init(clbm_ctx *ctx, void *state, const double *rho0, const double *u0);
 /* One time step, Steps 1-4 of Sec. II B fused in one kernel: pull-stream with
  * bounce-back (Eq. (8)), rho and u (Eq. (9)), raw moments (Eq. (4), (14)),
  * central shift N(u), collision (Eq. (5), (13), (15), (16)), back-shift N^-1 and
- * M^-1 (Eq. (7)).  src and dst are distinct state buffers. */
+ * M^-1 (Eq. (7)).  src and dst are distinct state buffers.  When every rate
+ * above second order is exactly 1 (s3 = s3b = s4 = s4b = s5 = s6 = 1, as in the
+ * simulations of Sec. III) the kernel forms only the moments up to second order:
+ * Eq. (5) then sets the higher ones to equilibrium + C/2 whatever their value. */
 int clbm_step(clbm_ctx *ctx, const void *src, void *dst);
 
-/* nsteps steps alternating between a and b, starting from the state in a.
- * The result is in a when nsteps is even and in b when it is odd. */
-int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps);
+/* nsteps steps from the state in a, using a and b as the two buffers; the
+ * buffer that holds the final state is returned in *result (host, may be
+ * NULL).  On periodic lattices without solid nodes and with FP32 storage,
+ * pairs of steps run as one fused launch that keeps the intermediate state on
+ * chip (bitwise the same result as two clbm_step calls); otherwise every step
+ * is one clbm_step.  nsteps >= 0. */
+int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result);
+
+/* Option flags (clbm_set_options). */
+#define CLBM_OPT_SINGLE_STEP 1u /* clbm_run launches one step at a time */
+
+/* Set the CLBM_OPT_* flags of a context (default 0). */
+int clbm_set_options(clbm_ctx *ctx, uint32_t options);
 
 /* Copy a state buffer (checkpoints).  src and dst distinct. */
 int clbm_copy(clbm_ctx *ctx, const void *src, void *dst);

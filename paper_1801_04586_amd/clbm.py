@@ -70,7 +70,8 @@ def load_library(path: str = LIB_PATH):
         "clbm_set_force": ([vp, dp, vp, ctypes.c_double], ctypes.c_int),
         "clbm_init": ([vp, vp, vp, vp], ctypes.c_int),
         "clbm_step": ([vp, vp, vp], ctypes.c_int),
-        "clbm_run": ([vp, vp, vp, i32], ctypes.c_int),
+        "clbm_run": ([vp, vp, vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "clbm_set_options": ([vp, ctypes.c_uint32], ctypes.c_int),
         "clbm_copy": ([vp, vp, vp], ctypes.c_int),
         "clbm_moments": ([vp, vp, vp, vp, dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "clbm_get_populations": ([vp, vp, vp], ctypes.c_int),
@@ -153,8 +154,14 @@ class Context:
     def step(self, src, dst):
         self._call("clbm_step", _ptr(src), _ptr(dst))
 
-    def run(self, a, b, nsteps: int):
-        self._call("clbm_run", _ptr(a), _ptr(b), ctypes.c_int32(int(nsteps)))
+    def run(self, a, b, nsteps: int) -> bool:
+        """Runs nsteps; returns True when the final state is in b."""
+        res = ctypes.c_void_p()
+        self._call("clbm_run", _ptr(a), _ptr(b), ctypes.c_int32(int(nsteps)), ctypes.byref(res))
+        return res.value == b.data_ptr()
+
+    def set_options(self, options: int):
+        self._call("clbm_set_options", ctypes.c_uint32(int(options)))
 
     def copy(self, src, dst):
         self._call("clbm_copy", _ptr(src), _ptr(dst))
@@ -271,11 +278,21 @@ class Lattice:
         n = int(n)
         if n <= 0:
             return self
-        self.ctx.run(self.state, self.other, n)
-        if n % 2:
+        if self.ctx.run(self.state, self.other, n):
             self.cur = 1 - self.cur
         self.t += n
         return self
+
+    def set_fused_steps(self, enabled: bool):
+        """Allow (default) or forbid the fused two-step launches of clbm_run."""
+        self.ctx.set_options(0 if enabled else 1)
+        self._fused = bool(enabled)
+
+    @property
+    def uses_fused_pairs(self) -> bool:
+        """Whether step(n) runs pairs of steps as one fused launch (the rule of clbm_run)."""
+        return (getattr(self, "_fused", True) and self.storage == "f32" and self.walls == (0, 0, 0)
+                and self.solid is None)
 
     def set_rates(self, rates):
         self.rates = np.asarray(rates, dtype=np.float64)

@@ -30,6 +30,7 @@ struct clbm_ctx {
     double *partials;  // [kMaxBlocks][kPartialStride]
     double *scal;      // [16] reduction results
     uint32_t *links;   // [N] link table (k_links) when the lattice has solid nodes, else NULL
+    uint32_t options;  // CLBM_OPT_* flags
     char err[512];
 };
 
@@ -144,17 +145,72 @@ unsigned stride_blocks(const clbm_ctx *c)
     return b < static_cast<unsigned>(kMaxBlocks) ? b : static_cast<unsigned>(kMaxBlocks);
 }
 
+// Every rate above second order (s3, s3b, s4, s4b, s5, s6) equal to one: the
+// collision then needs no moments beyond second order (collide_high1).
+bool high_rates_one(const clbm_ctx *c)
+{
+    for (int k = 4; k < 10; ++k)
+        if (c->d.s[k] != 1.0) return false;
+    return true;
+}
+
 int launch_step(clbm_ctx *c, const void *src, void *dst)
 {
+    const bool high1 = high_rates_one(c);
     return dispatch(c, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
         using R = typename Vt::R;
-        hipLaunchKernelGGL((k_step<S, Vt::check, Vt::solid, Vt::field>), dim3(node_blocks(c)), dim3(kBlock), 0,
-                           c->stream, static_cast<const S *>(src), static_cast<S *>(dst), c->geom, c->links,
-                           static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
-        return check_launch(c, "step kernel launch");
+        auto go = [&](auto h) {
+            constexpr bool H = decltype(h)::value;
+            hipLaunchKernelGGL((k_step<S, Vt::check, Vt::solid, Vt::field, H>), dim3(node_blocks(c)), dim3(kBlock),
+                               0, c->stream, static_cast<const S *>(src), static_cast<S *>(dst), c->geom, c->links,
+                               static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
+            return check_launch(c, "step kernel launch");
+        };
+        return high1 ? go(std::true_type{}) : go(std::false_type{});
     });
+}
+
+// Two fused steps per launch apply to periodic lattices without solids with FP32
+// storage.  FP64 does not fit the LDS ring at this tile size, and for 16-bit
+// storage (half the bytes of FP32) the single-step kernel is faster: the fused
+// kernel's cost per step is set by its arithmetic and barriers, not by memory.
+bool fused_pairs(const clbm_ctx *c)
+{
+    return !(c->options & CLBM_OPT_SINGLE_STEP) && c->d.storage == CLBM_F32 && !c->links && !c->d.wall[0] &&
+           !c->d.wall[1] && !c->d.wall[2];
+}
+
+int launch_step2(clbm_ctx *c, const void *src, void *dst)
+{
+    T2Geom tg;
+    tg.tiles_x = (c->geom.nx + kT2X - 1) / kT2X;
+    tg.tiles_y = (c->geom.ny + kT2Y - 1) / kT2Y;
+    const uint32_t tiles = tg.tiles_x * tg.tiles_y;
+    // about 2048 blocks (8 per CU) when the lattice allows, chunks of at least 8 planes
+    uint32_t nchunks = (2048 + tiles - 1) / tiles;
+    const uint32_t max_chunks = (c->geom.nz + 7) / 8;
+    if (nchunks > max_chunks) nchunks = max_chunks;
+    if (nchunks < 1) nchunks = 1;
+    tg.zchunk = (c->geom.nz + nchunks - 1) / nchunks;
+    nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
+    const unsigned blocks = tiles * nchunks;
+    const bool high1 = high_rates_one(c);
+    auto go = [&](auto tag, auto field_tag) {
+        using S = decltype(tag);
+        using R = typename Traits<S>::R;
+        constexpr bool FIELD = decltype(field_tag)::value;
+        auto launch = [&](auto h) {
+            constexpr bool H = decltype(h)::value;
+            hipLaunchKernelGGL((k_step2<S, FIELD, H>), dim3(blocks), dim3(kT2Block), 0, c->stream,
+                               static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg,
+                               static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
+            return check_launch(c, "fused two-step kernel launch");
+        };
+        return high1 ? launch(std::true_type{}) : launch(std::false_type{});
+    };
+    return c->d.force != nullptr ? go(float{}, std::true_type{}) : go(float{}, std::false_type{});
 }
 
 }  // namespace
@@ -213,6 +269,7 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
         return rc;
     }
     c->links = nullptr;
+    c->options = 0;
     if (desc->solid) {
         e = hipMalloc(&c->links, sizeof(uint32_t) * c->nodes);
         if (e == hipSuccess) {
@@ -300,15 +357,37 @@ int clbm_step(clbm_ctx *ctx, const void *src, void *dst)
     return launch_step(ctx, src, dst);
 }
 
-int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps)
+int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result)
 {
     if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
     if (!a || !b || !aligned(a) || !aligned(b) || a == b) return fail(ctx, CLBM_EINVAL, "bad state buffers");
     if (nsteps < 0) return fail(ctx, CLBM_EINVAL, "nsteps < 0");
-    for (int32_t k = 0; k < nsteps; ++k) {
-        const int rc = (k & 1) ? launch_step(ctx, b, a) : launch_step(ctx, a, b);
+    void *cur = a, *nxt = b;
+    int32_t k = 0;
+    if (fused_pairs(ctx))
+        for (; k + 2 <= nsteps; k += 2) {
+            const int rc = launch_step2(ctx, cur, nxt);
+            if (rc) return rc;
+            void *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+    for (; k < nsteps; ++k) {
+        const int rc = launch_step(ctx, cur, nxt);
         if (rc) return rc;
+        void *t = cur;
+        cur = nxt;
+        nxt = t;
     }
+    if (result) *result = cur;
+    return CLBM_OK;
+}
+
+int clbm_set_options(clbm_ctx *ctx, uint32_t options)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (options & ~static_cast<uint32_t>(CLBM_OPT_SINGLE_STEP)) return fail(ctx, CLBM_EINVAL, "unknown option bits");
+    ctx->options = options;
     return CLBM_OK;
 }
 

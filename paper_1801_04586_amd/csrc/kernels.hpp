@@ -115,10 +115,8 @@ __device__ __forceinline__ void node_coords(const Geom &g, uint32_t n, uint32_t 
     y = yz - z * g.ny;
 }
 
-__device__ __forceinline__ void neighbours(const Geom &g, uint32_t n, Nbr &nb)
+__device__ __forceinline__ void neighbours_xyz(const Geom &g, uint32_t x, uint32_t y, uint32_t z, Nbr &nb)
 {
-    uint32_t x, y, z;
-    node_coords(g, n, x, y, z);
     axis_sources(x, g.nx, g.wall[0], nb.xs, nb.vx);
     axis_sources(y, g.ny, g.wall[1], nb.ys, nb.vy);
     axis_sources(z, g.nz, g.wall[2], nb.zs, nb.vz);
@@ -127,6 +125,13 @@ __device__ __forceinline__ void neighbours(const Geom &g, uint32_t n, Nbr &nb)
         nb.ys[k] *= g.nx;
         nb.zs[k] *= g.nxy;
     }
+}
+
+__device__ __forceinline__ void neighbours(const Geom &g, uint32_t n, Nbr &nb)
+{
+    uint32_t x, y, z;
+    node_coords(g, n, x, y, z);
+    neighbours_xyz(g, x, y, z, nb);
 }
 
 // Is the link pulled by slot t open (neighbour x - e exists and is fluid)?  When
@@ -144,27 +149,75 @@ __device__ __forceinline__ bool link_open(const Nbr &nb, uint32_t lm, uint32_t &
         return nb.vx[a] && nb.vy[b] && nb.vz[c];
 }
 
+// Element at a 32-bit byte offset from a wavefront-uniform base.  Every
+// population plane has its own base (kept in scalar registers), so each load or
+// store needs one 32-bit per-lane offset instead of a 64-bit per-lane address.
+// A plane therefore spans less than 4 GiB: N * sizeof(element) < 2^32.
+template <typename T>
+__device__ __forceinline__ T load_at(const T *__restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void store_at(T *__restrict__ base, uint32_t byte_off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
+template <typename S, bool CHECK, bool SOLID, bool REV, typename R>
+__device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
+                                             uint32_t lm, R (&v)[27]);
+
 // Gather of Eq. (8): v[t] = population of slot t arriving at node n, as a real
 // (the stored value, deviation or not).  REV gathers along +e instead (adjoint).
+// With walls or solids, a wavefront whose nodes all have their 26 links open
+// (the common case) takes the unchecked path; only wavefronts touching a wall or
+// a solid test every link.
+constexpr uint32_t kAllLinks = (1u << 27) - 1u;
+
 template <typename S, bool CHECK, bool SOLID, bool REV, typename R>
 __device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb, uint32_t lm,
                                        R (&v)[27])
 {
+    if constexpr (CHECK) {
+        bool open;
+        if constexpr (SOLID)
+            open = lm == kAllLinks;
+        else
+            open = nb.vx[0] && nb.vx[2] && nb.vy[0] && nb.vy[2] && nb.vz[0] && nb.vz[2];
+        if (__all(open))
+            gather_links<S, false, false, REV>(buf, N, n, nb, lm, v);
+        else
+            gather_links<S, true, SOLID, REV>(buf, N, n, nb, lm, v);
+    } else {
+        gather_links<S, false, false, REV>(buf, N, n, nb, lm, v);
+    }
+}
+
+template <typename S, bool CHECK, bool SOLID, bool REV, typename R>
+__device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
+                                             uint32_t lm, R (&v)[27])
+{
+    constexpr uint32_t es = sizeof(S);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         constexpr int i = pop_of_slot(t);
         const S *__restrict__ Pi = buf + static_cast<size_t>(i) * N;
         if constexpr (t == 13) {
-            v[t] = static_cast<R>(to_real(Pi[n]));
+            v[t] = static_cast<R>(to_real(load_at(Pi, n * es)));
         } else {
             uint32_t off;
             const bool ok = link_open<t, REV, SOLID>(nb, lm, off);
             if constexpr (CHECK) {
                 constexpr int ib = pop_of_slot(26 - t);
-                const S *p = ok ? (Pi + off) : (buf + static_cast<size_t>(ib) * N + n);
-                v[t] = static_cast<R>(to_real(*p));
+                S val;
+                if (ok)
+                    val = load_at(Pi, off * es);
+                else
+                    val = load_at(buf + static_cast<size_t>(ib) * N, n * es);
+                v[t] = static_cast<R>(to_real(val));
             } else {
-                v[t] = static_cast<R>(to_real(Pi[off]));
+                v[t] = static_cast<R>(to_real(load_at(Pi, off * es)));
             }
         }
     });
@@ -221,18 +274,39 @@ struct Forcing {
     R scale;  // multiplies the per-node field
 };
 
+// Raw per-node field values (zero without a field) and the force they give.
 template <bool FIELD, typename R>
-__device__ __forceinline__ void force_at(const Forcing<R> &fo, const R *__restrict__ field, uint32_t N, uint32_t n,
-                                         R &Fx, R &Fy, R &Fz)
+__device__ __forceinline__ void load_field(const R *__restrict__ field, uint32_t N, uint32_t n, R &fx, R &fy, R &fz)
+{
+    fx = fy = fz = R(0);
+    if constexpr (FIELD) {
+        const uint32_t off = n * static_cast<uint32_t>(sizeof(R));
+        fx = load_at(field, off);
+        fy = load_at(field + N, off);
+        fz = load_at(field + 2 * static_cast<size_t>(N), off);
+    }
+}
+
+template <bool FIELD, typename R>
+__device__ __forceinline__ void force_from(const Forcing<R> &fo, R fx, R fy, R fz, R &Fx, R &Fy, R &Fz)
 {
     Fx = fo.F[0];
     Fy = fo.F[1];
     Fz = fo.F[2];
     if constexpr (FIELD) {
-        Fx = fma(fo.scale, field[n], Fx);
-        Fy = fma(fo.scale, field[N + n], Fy);
-        Fz = fma(fo.scale, field[2 * static_cast<size_t>(N) + n], Fz);
+        Fx = fma(fo.scale, fx, Fx);
+        Fy = fma(fo.scale, fy, Fy);
+        Fz = fma(fo.scale, fz, Fz);
     }
+}
+
+template <bool FIELD, typename R>
+__device__ __forceinline__ void force_at(const Forcing<R> &fo, const R *__restrict__ field, uint32_t N, uint32_t n,
+                                         R &Fx, R &Fy, R &Fz)
+{
+    R fx, fy, fz;
+    load_field<FIELD>(field, N, n, fx, fy, fz);
+    force_from<FIELD>(fo, fx, fy, fz, Fx, Fy, Fz);
 }
 
 // ------------------------------------------------------------------ XCD-aware block order
@@ -248,12 +322,35 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
 }
 
 // ------------------------------------------------------------------ forward step
+// Steps 1-3 of Sec. II B on one node's deviations d = f - w (in place, registers).
+// HIGH1: every rate above second order is one (collide_high1).
+template <bool HIGH1 = false, typename R>
+__device__ __forceinline__ void node_update(R (&v)[27], R Fx, R Fy, R Fz, const Rates<R> &rt)
+{
+    if constexpr (HIGH1) {
+        R ux, uy, uz;
+        collide_high1(v, Fx, Fy, Fz, rt, ux, uy, uz);
+        reconstruct(v, ux, uy, uz);
+        return;
+    }
+    raw_moments(v);  // Eq. (4), (14): T = M d
+    const R drho = v[slot(0, 0, 0)];
+    const R inv_rho = R(1) / (R(1) + drho);  // Eq. (9)
+    const R ux = (v[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho;
+    const R uy = (v[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho;
+    const R uz = (v[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho;
+    central_shift(v, ux, uy, uz);  // T~ = N(u) T
+    const AxisU<R> X(ux), Y(uy), Z(uz);
+    collide(v, drho, X, Y, Z, Fx, Fy, Fz, rt);  // Eq. (5)
+    reconstruct(v, ux, uy, uz);                 // Eq. (7): N^-1 then M^-1
+}
+
 // One fused time step on one node per thread (Steps 1-4 of Sec. II B).
 // A solid node reads nothing but still runs the arithmetic on the rest state and
 // stores its (never read) entries, so that every wavefront writes whole cache
 // lines: lanes that skipped their stores would leave partially written lines,
 // which cost far more memory time than the extra bytes.
-template <typename S, bool CHECK, bool SOLID, bool FIELD>
+template <typename S, bool CHECK, bool SOLID, bool FIELD, bool HIGH1>
 __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src, S *__restrict__ dst, const Geom &g,
                                           const uint32_t *__restrict__ links,
                                           const typename Traits<S>::R *__restrict__ field,
@@ -275,35 +372,165 @@ __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src,
         sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });
     }
 
-    raw_moments(v);  // Eq. (4), (14): T = M d
-    const R drho = v[slot(0, 0, 0)];
     R Fx, Fy, Fz;
     force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
-    const R inv_rho = R(1) / (R(1) + drho);  // Eq. (9)
-    const R ux = (v[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho;
-    const R uy = (v[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho;
-    const R uz = (v[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho;
-    central_shift(v, ux, uy, uz);  // T~ = N(u) T
-    const AxisU<R> X(ux), Y(uy), Z(uz);
-    collide(v, drho, X, Y, Z, Fx, Fy, Fz, rt);  // Eq. (5)
-    reconstruct(v, ux, uy, uz);                 // Eq. (7): N^-1 then M^-1
+    node_update<HIGH1>(v, Fx, Fy, Fz, rt);
 
+    const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         R val = v[t];
         if constexpr (!Traits<S>::kDev) val += weight_of_slot<R>(t);
-        dst[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = to_store<S>(val);
+        store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.N, nb_off, to_store<S>(val));
     });
 }
 
-template <typename S, bool CHECK, bool SOLID, bool FIELD>
+template <typename S, bool CHECK, bool SOLID, bool FIELD, bool HIGH1>
 __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *__restrict__ dst, Geom g,
                                                  const uint32_t *__restrict__ links,
                                                  const typename Traits<S>::R *__restrict__ field,
                                                  Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
 {
-    step_node<S, CHECK, SOLID, FIELD>(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x, src, dst, g, links,
+    step_node<S, CHECK, SOLID, FIELD, HIGH1>(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x, src, dst, g, links,
                                       field, fo, rt);
+}
+
+// ------------------------------------------------------------------ two fused steps (temporal blocking)
+// Two time steps per launch on periodic lattices without solid nodes.  A block
+// owns a 32 x 8 tile of (x, y) columns and marches along a chunk of z planes.
+// For each plane it first runs step t -> t+1 on the tile plus a one-node halo
+// (34 x 10 nodes, pulling from HBM), keeping the results in LDS, and then step
+// t+1 -> t+2 on the tile plane below, pulling those results from LDS and
+// writing to HBM.  The intermediate state never leaves the chip, so HBM moves
+// about 1.33 x 27 reads (the halo) and 27 writes per node for two updates
+// instead of 2 x (27 + 27).  Intermediate values are rounded to the storage
+// type exactly as a stored state would be, so the result is bitwise that of
+// two single steps.
+//
+// LDS ring: step t+2 at plane z pulls the e_z = -1 populations from plane z+1,
+// e_z = 0 from plane z and e_z = +1 from plane z-1 of the intermediate state.
+// Grouped by e_z, a plane's 9 populations with e_z = -1 are needed for one
+// plane iteration, those with e_z = 0 for two and those with e_z = +1 for
+// three, so the ring holds 1 + 2 + 3 plane slots of 9 x 340 values (73 KB,
+// two blocks per CU).
+constexpr int kT2X = 32, kT2Y = 8;
+constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 340 nodes
+constexpr int kT2Block = 384;                                               // >= kT2H, six wavefronts
+
+struct T2Geom {
+    uint32_t tiles_x, tiles_y, zchunk;
+};
+
+__device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
+{
+    int r = c % static_cast<int>(n);
+    return static_cast<uint32_t>(r < 0 ? r + static_cast<int>(n) : r);
+}
+
+template <typename S, bool FIELD, bool HIGH1>
+__global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg,
+                                                    const typename Traits<S>::R *__restrict__ field,
+                                                    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
+{
+    using R = typename Traits<S>::R;
+    static_assert(std::is_same<R, float>::value, "the LDS ring holds FP32 values");
+    __shared__ float ring[6][9][kT2H];  // [0]: e_z=-1 (1 slot), [1..2]: e_z=0 (2 slots), [3..5]: e_z=+1 (3 slots)
+
+    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t tx = b % tg.tiles_x, rest = b / tg.tiles_x;
+    const uint32_t ty = rest % tg.tiles_y, zc = rest / tg.tiles_y;
+    const int x0 = static_cast<int>(tx) * kT2X, y0 = static_cast<int>(ty) * kT2Y;
+    const int z0 = static_cast<int>(zc * tg.zchunk);
+    const int z1 = min(z0 + static_cast<int>(tg.zchunk), static_cast<int>(g.nz));
+    const int tid = threadIdx.x;
+
+    // step t -> t+1 role: halo node (hx, hy)
+    const bool ha = tid < kT2H;
+    const int hx = tid % kT2HX, hy = tid / kT2HX;
+    const uint32_t gx = wrap_coord(x0 - 1 + hx, g.nx), gy = wrap_coord(y0 - 1 + hy, g.ny);
+    // step t+1 -> t+2 role: tile node (cx, cy)
+    const int cx = tid % kT2X, cy = tid / kT2X;
+    const bool ca = tid < kT2X * kT2Y && x0 + cx < static_cast<int>(g.nx) && y0 + cy < static_cast<int>(g.ny);
+
+    // ring slot of plane p (unwrapped) for the group with e_z index c = e_z + 1
+    auto ring_slot = [&](int c, int p) {
+        const int q = p - z0 + 1;  // >= 0 for every plane touched
+        return c == 0 ? 0 : (c == 1 ? 1 + (q & 1) : 3 + q % 3);
+    };
+
+    // The first step is split into its loads (into registers) and its arithmetic, so
+    // that the loads of plane p+1 are in flight while the block works on plane p.
+    // prefetched values stay in the storage type: a conversion right after the load
+    // would make the wavefront wait for it (and, counters being in order, for all
+    // earlier loads) before the barrier
+    S pre[27];
+    R pFx = R(0), pFy = R(0), pFz = R(0);
+    auto load_first = [&](int p) {
+        if (!ha) return;
+        const uint32_t pz = wrap_coord(p, g.nz);
+        const uint32_t n = gx + g.nx * (gy + g.ny * pz);
+        Nbr nb;
+        neighbours_xyz(g, gx, gy, pz, nb);
+        constexpr uint32_t es = sizeof(S);
+        sfor<0, 27>([&](auto TT) {
+            constexpr int t = decltype(TT)::value;
+            uint32_t off;
+            link_open<t, false, false>(nb, 0u, off);
+            pre[t] = load_at(src + static_cast<size_t>(pop_of_slot(t)) * g.N, off * es);
+        });
+        load_field<FIELD>(field, g.N, n, pFx, pFy, pFz);  // raw values: combined only when used
+    };
+    auto first_step = [&](int p) {
+        if (!ha) return;
+        R v[27];
+        sfor<0, 27>([&](auto T) { v[decltype(T)::value] = to_real(pre[decltype(T)::value]); });
+        R Fx, Fy, Fz;
+        force_from<FIELD>(fo, pFx, pFy, pFz, Fx, Fy, Fz);
+        node_update<HIGH1>(v, Fx, Fy, Fz, rt);
+        const int sA = ring_slot(0, p), sB = ring_slot(1, p), sC = ring_slot(2, p);
+        sfor<0, 27>([&](auto TT) {
+            constexpr int t = decltype(TT)::value;
+            constexpr int c = sc(t), j = 3 * sa(t) + sb(t);
+            const float val = static_cast<float>(to_store<S>(v[t]));  // the value a stored state would hold
+            ring[c == 0 ? sA : (c == 1 ? sB : sC)][j][tid] = val;
+        });
+    };
+
+    auto second_step = [&](int z) {
+        if (!ca) return;
+        const uint32_t zz = wrap_coord(z, g.nz);
+        const uint32_t n = static_cast<uint32_t>(x0 + cx) + g.nx * (static_cast<uint32_t>(y0 + cy) + g.ny * zz);
+        const int sA = ring_slot(0, z + 1), sB = ring_slot(1, z), sC = ring_slot(2, z - 1);
+        R v[27];
+        sfor<0, 27>([&](auto TT) {
+            constexpr int t = decltype(TT)::value;
+            constexpr int a = sa(t), bb = sb(t), c = sc(t), j = 3 * a + bb;
+            // pull from (x - e_x, y - e_y) of the halo tile, e = (a - 1, b - 1)
+            const int h = (cy + 2 - bb) * kT2HX + (cx + 2 - a);
+            v[t] = ring[c == 0 ? sA : (c == 1 ? sB : sC)][j][h];
+        });
+        R Fx, Fy, Fz;
+        force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+        node_update<HIGH1>(v, Fx, Fy, Fz, rt);
+        const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
+        sfor<0, 27>([&](auto TT) {
+            constexpr int t = decltype(TT)::value;
+            store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.N, nb_off, to_store<S>(v[t]));
+        });
+    };
+
+    load_first(z0 - 1);
+    first_step(z0 - 1);
+    load_first(z0);
+    first_step(z0);
+    load_first(z0 + 1);
+    for (int z = z0; z < z1; ++z) {
+        __syncthreads();  // the previous plane's pulls from the ring are done
+        first_step(z + 1);
+        if (z + 1 < z1) load_first(z + 2);  // in flight during the second step below
+        __syncthreads();  // plane z+1 is in the ring
+        second_step(z);
+    }
 }
 
 // ------------------------------------------------------------------ block reductions (FP64, fixed order)
@@ -669,9 +896,10 @@ __device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const
         a[slot(0, 0, 0)] += rhob;
         raw_moments_T(a);  // lambda(t) = M^T a
 
+        const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(R));
         sfor<0, 27>([&](auto TT) {
             constexpr int t = decltype(TT)::value;
-            lam_out[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = a[t];
+            store_at(lam_out + static_cast<size_t>(pop_of_slot(t)) * g.N, nb_off, a[t]);
         });
         if (dJdF) {
             dJdF[n] = gFx + Fbx;

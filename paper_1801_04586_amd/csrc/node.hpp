@@ -272,6 +272,101 @@ __device__ __forceinline__ void collide(R (&v)[27], R drho, const AxisU<R> &X, c
     v[iz] -= fma(s.s[R_S2], nz, tr);
 }
 
+// Collision when every rate above second order is one (s3 = s3b = s4 = s4b = s5 =
+// s6 = 1, the setting of the paper's simulations, Sec. III).  Eq. (5) then sets
+// each central moment of order >= 3 to its equilibrium plus C/2, independently
+// of the pre-collision value, so only the raw and central moments up to second
+// order are formed.  On entry v holds the deviations d (populations); on exit
+// the post-collision central moments minus those of w, as collide() leaves them.
+template <typename R>
+__device__ __forceinline__ void collide_high1(R (&v)[27], R Fx, R Fy, R Fz, const Rates<R> &s, R &ux_out, R &uy_out,
+                                              R &uz_out)
+{
+    constexpr R cs2 = R(1.0 / 3.0), cs4 = R(1.0 / 9.0);
+    // z pass, complete: v[slot(a, b, p)] = moment p along z of the (a, b) column
+    axis_pass<2>(v, [](R &a, R &b, R &c) {
+        const R k0 = a + b + c, k1 = c - a, k2 = c + a;
+        a = k0;
+        b = k1;
+        c = k2;
+    });
+    // y pass: only (n, p) with n + p <= 2 are needed
+    R Y[3][3][3];  // [a][n][p]
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R m0 = v[slot(a, 0, 0)], z0 = v[slot(a, 1, 0)], p0 = v[slot(a, 2, 0)];
+        Y[a][0][0] = m0 + z0 + p0;
+        Y[a][1][0] = p0 - m0;
+        Y[a][2][0] = p0 + m0;
+        const R m1 = v[slot(a, 0, 1)], z1 = v[slot(a, 1, 1)], p1 = v[slot(a, 2, 1)];
+        Y[a][0][1] = m1 + z1 + p1;
+        Y[a][1][1] = p1 - m1;
+        Y[a][0][2] = v[slot(a, 0, 2)] + v[slot(a, 1, 2)] + v[slot(a, 2, 2)];
+    }
+    // x pass: raw moments T_d(m, n, p) with m + n + p <= 2
+    const R t000 = Y[0][0][0] + Y[1][0][0] + Y[2][0][0];
+    const R t100 = Y[2][0][0] - Y[0][0][0];
+    const R t200 = Y[2][0][0] + Y[0][0][0];
+    const R t010 = Y[0][1][0] + Y[1][1][0] + Y[2][1][0];
+    const R t110 = Y[2][1][0] - Y[0][1][0];
+    const R t001 = Y[0][0][1] + Y[1][0][1] + Y[2][0][1];
+    const R t101 = Y[2][0][1] - Y[0][0][1];
+    const R t011 = Y[0][1][1] + Y[1][1][1] + Y[2][1][1];
+    const R t020 = Y[0][2][0] + Y[1][2][0] + Y[2][2][0];
+    const R t002 = Y[0][0][2] + Y[1][0][2] + Y[2][0][2];
+    // Eq. (9)
+    const R drho = t000;
+    const R inv_rho = R(1) / (R(1) + drho);
+    const R ux = (t100 + R(0.5) * Fx) * inv_rho;
+    const R uy = (t010 + R(0.5) * Fy) * inv_rho;
+    const R uz = (t001 + R(0.5) * Fz) * inv_rho;
+    ux_out = ux;
+    uy_out = uy;
+    uz_out = uz;
+    const AxisU<R> X(ux), Y_(uy), Z(uz);
+    // central second moments of d about u (N(u) restricted to order 2)
+    const R c200 = fma(ux, fma(ux, t000, R(-2) * t100), t200);
+    const R c020 = fma(uy, fma(uy, t000, R(-2) * t010), t020);
+    const R c002 = fma(uz, fma(uz, t000, R(-2) * t001), t002);
+    const R c110 = fma(ux * uy, t000, fma(-ux, t010, fma(-uy, t100, t110)));
+    const R c101 = fma(ux * uz, t000, fma(-ux, t001, fma(-uz, t100, t101)));
+    const R c011 = fma(uy * uz, t000, fma(-uy, t001, fma(-uz, t010, t011)));
+    // post-collision central moments minus those of w
+    sfor<0, 27>([&](auto T) {
+        constexpr int t = decltype(T)::value;
+        constexpr int m = sa(t), n = sb(t), p = sc(t);
+        constexpr int ones = (m == 1) + (n == 1) + (p == 1);
+        constexpr int order = m + n + p;
+        if constexpr (order == 0) {
+            v[t] = drho;
+        } else if constexpr (order == 1) {
+            v[t] = m == 1 ? fma(R(0.5), Fx, ux) : (n == 1 ? fma(R(0.5), Fy, uy) : fma(R(0.5), Fz, uz));
+        } else if constexpr (order == 2 && ones == 2) {
+            const R c = m == 0 ? c011 : (n == 0 ? c101 : c110);
+            const R neq = c + g_term<m, n, p>(X, Y_, Z);
+            v[t] = fma(-s.s[R_S2], neq, c);
+        } else if constexpr (order >= 3) {
+            // equilibrium + C/2: drho E - G + C/2
+            constexpr R E = R(e_of(m) * e_of(n) * e_of(p));
+            R out = -g_term<m, n, p>(X, Y_, Z);
+            if constexpr (ones == 0) out = fma(drho, E, out);
+            if constexpr (ones == 1) {
+                constexpr R cf = R(0.5) * (order == 3 ? cs2 : cs4);
+                out = fma(cf, m == 1 ? Fx : (n == 1 ? Fy : Fz), out);
+            }
+            v[t] = out;
+        }
+    });
+    // block of Eq. (13) on (k200, k020, k002)
+    const R nx = c200 + X.u2 - drho * cs2;
+    const R ny = c020 + Y_.u2 - drho * cs2;
+    const R nz = c002 + Z.u2 - drho * cs2;
+    const R tr = s.sm * (nx + ny + nz);
+    v[slot(2, 0, 0)] = c200 - fma(s.s[R_S2], nx, tr);
+    v[slot(0, 2, 0)] = c020 - fma(s.s[R_S2], ny, tr);
+    v[slot(0, 0, 2)] = c002 - fma(s.s[R_S2], nz, tr);
+}
+
 // Deviation of the generalized equilibrium (Sec. II B) in central-moment space:
 // T_eq - N(u) M w = drho E - G.  Feeding it to reconstruct() gives f_eq - w.
 template <typename R>

@@ -111,7 +111,8 @@ def test_create_rejects_bad_storage_and_reserved():
 def test_calls_on_null_context_fail_cleanly():
     L = _lib()
     assert L.clbm_step(None, None, None) == 1
-    assert L.clbm_run(None, None, None, 3) == 1
+    assert L.clbm_run(None, None, None, 3, None) == 1
+    assert L.clbm_set_options(None, 0) == 1
     assert L.clbm_moments(None, None, None, None, None, None) == 1
     assert L.clbm_adjoint_step(None, None, None, None, None, None) == 1
     assert L.clbm_destroy(None) == 0

@@ -24,6 +24,9 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 RATES = np.array([1.0, 1.0, 1.6, 1.2, 1.3, 0.9, 1.1, 1.25, 0.95, 1.05])
+# every rate above second order equal to one (the setting of Sec. III): the kernels
+# take a separate collision path for it
+RATES_H1 = np.array([1.0, 1.0, 1.6, 1.2, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
 TOL = {"f64": 1e-13, "f32": 5e-8, "f16": 1e-5, "bf16": 8e-5}
 
 
@@ -44,17 +47,18 @@ def _fluid(solid, shape):
     return np.ones(shape, bool) if solid is None else (solid == 0)
 
 
-def _compare(dims, walls, storage, steps, seed, with_field=True, solid_frac=0.0, force=(2e-5, -1e-5, 3e-6)):
+def _compare(dims, walls, storage, steps, seed, with_field=True, solid_frac=0.0, force=(2e-5, -1e-5, 3e-6),
+             rates=RATES):
     solid = workloads.random_solids(dims, solid_frac, seed + 5) if solid_frac else None
     g, f0 = _random_start(dims, walls, seed, solid)
     field = workloads.gaussian_force(dims, 1e-4, seed + 2) if with_field else None
-    lat = _lattice(dims, walls, storage, force=force, field=field, solid=solid)
+    lat = _lattice(dims, walls, storage, rates=rates, force=force, field=field, solid=solid)
     lat.set_populations(torch.from_numpy(f0))
     start = lat.populations().cpu().numpy()  # f0 rounded to the storage type
     fl = _fluid(solid, g.shape)
     if storage == "f64":
         assert np.array_equal(start[:, fl], f0[:, fl])
-    ref = oracle.run(g, start, RATES, steps, force=force, force_field=field, solid=solid)
+    ref = oracle.run(g, start, rates, steps, force=force, force_field=field, solid=solid)
     lat.step(steps)
     got = lat.populations().cpu().numpy()
     lat.close()
@@ -127,6 +131,34 @@ def test_step_parity_reduced_storage_one_step(storage, walls, solid_frac):
 
 def test_step_parity_f32_ten_steps():
     assert _compare((13, 9, 7), (0, 1, 0), "f32", 10, 43, solid_frac=0.1) < 2e-7
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("walls,solid_frac,with_field", [((0, 0, 0), 0.0, True), ((0, 1, 1), 0.0, False),
+                                                         ((1, 0, 1), 0.2, True)])
+def test_step_parity_high_order_rates_one(storage, walls, solid_frac, with_field):
+    steps = 5 if storage in ("f64", "f32") else 1
+    tol = {"f64": 1e-13, "f32": 1.5e-7}.get(storage, TOL[storage])
+    err = _compare((23, 19, 13), walls, storage, steps, 61, with_field=with_field, solid_frac=solid_frac,
+                   rates=RATES_H1)
+    assert err < tol, err
+
+
+def test_high_order_rates_one_path_agrees_with_general_path():
+    """Rates one ulp above one take the general collision; the results may differ
+    only by rounding (FP64)."""
+    dims, walls = (17, 11, 9), (0, 1, 0)
+    g, f0 = _random_start(dims, walls, 71)
+    near = RATES_H1.copy()
+    near[4:] = np.nextafter(1.0, 2.0)
+    out = []
+    for r in (RATES_H1, near):
+        lat = _lattice(dims, walls, "f64", rates=r, force=(1e-5, 0, 0))
+        lat.set_populations(torch.from_numpy(f0))
+        lat.step(8)
+        out.append(lat.populations().cpu().numpy())
+        lat.close()
+    assert np.max(np.abs(out[0] - out[1])) < 1e-13
 
 
 # ----------------------------------------------------------------------------- moments and conservation
