@@ -1,4 +1,5 @@
-"""FP64 CPU oracle of the D3Q27 cascaded LBM of arXiv:1801.04586 (Fei, Luo & Li).
+"""FP64 CPU oracle of the D3Q27 (and, Appendix A, D3Q19) cascaded LBM of
+arXiv:1801.04586 (Fei, Luo & Li).
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
@@ -8,8 +9,9 @@ definitions, Steps 1-4 of Sec. II B), and this module only marshals numpy
 arrays into it.
 
 Array conventions (all float64 unless stated):
-  * populations ``f``: shape (27, nz, ny, nx), population order of Eq. (1);
-    these are the *pre-collision* populations f(x, t) of the paper;
+  * populations ``f``: shape (27, nz, ny, nx), population order of Eq. (1)
+    (D3Q19: (19, nz, ny, nx), order of Eq. (A1)); these are the
+    *pre-collision* populations f(x, t) of the paper;
   * velocity ``u``: shape (3, nz, ny, nx); density ``rho``: (nz, ny, nx);
   * force field: (3, nz, ny, nx) force density, added to the uniform force;
   * solid mask: uint8 (nz, ny, nx), 1 = solid.
@@ -69,6 +71,20 @@ def lib():
         L.orc_adjoint_step.argtypes = [ip, dp, dp, dp, u8, dp, dp, dp, dp, dp]
         L.orc_loss_seed.argtypes = [ip, dp, dp, u8, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        for name in ("orc19_matrix_M", "orc19_matrix_Minv"):
+            getattr(L, name).argtypes = [dp]
+        L.orc19_matrix_K.argtypes = [dp, dp]
+        L.orc19_matrix_N.argtypes = [dp, dp]
+        L.orc19_matrix_S.argtypes = [dp, dp]
+        L.orc19_teq.argtypes = [ctypes.c_double, dp]
+        L.orc19_cvec.argtypes = [dp, dp]
+        L.orc19_velocities.argtypes = [ip]
+        L.orc19_exponents.argtypes = [ip]
+        L.orc19_collide.argtypes = [dp, dp, dp, dp]
+        L.orc19_equilibrium.argtypes = [ctypes.c_double, dp, dp]
+        L.orc19_step.argtypes = [ip, dp, dp, dp, u8, dp, dp]
+        L.orc19_macro.argtypes = [ip, dp, dp, u8, dp, dp, dp]
+        L.orc19_init.argtypes = [ip, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -226,39 +242,124 @@ def equilibrium(rho, u) -> np.ndarray:
     return out
 
 
+# --------------------------------------------------------------------------- D3Q19 (Appendix A)
+def q19_velocities() -> np.ndarray:
+    """Eq. (A1) velocities, shape (19, 3) int."""
+    e = np.zeros(57, dtype=np.int32)
+    lib().orc19_velocities(e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return e.reshape(19, 3).astype(np.int64)
+
+
+def q19_exponents() -> np.ndarray:
+    """Eq. (A2) exponents of the 19 moments, shape (19, 3) int."""
+    p = np.zeros(57, dtype=np.int32)
+    lib().orc19_exponents(p.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return p.reshape(19, 3).astype(np.int64)
+
+
+def q19_matrix_M() -> np.ndarray:
+    out = np.zeros((19, 19))
+    lib().orc19_matrix_M(_d(out))
+    return out
+
+
+def q19_matrix_Minv() -> np.ndarray:
+    out = np.zeros((19, 19))
+    assert lib().orc19_matrix_Minv(_d(out)) == 0
+    return out
+
+
+def q19_matrix_K(u) -> np.ndarray:
+    out = np.zeros((19, 19))
+    lib().orc19_matrix_K(_d(_vec3(u)), _d(out))
+    return out
+
+
+def q19_matrix_N(u) -> np.ndarray:
+    out = np.zeros((19, 19))
+    lib().orc19_matrix_N(_d(_vec3(u)), _d(out))
+    return out
+
+
+def q19_matrix_S(s) -> np.ndarray:
+    out = np.zeros((19, 19))
+    lib().orc19_matrix_S(_d(_rates(s)), _d(out))
+    return out
+
+
+def q19_teq(rho) -> np.ndarray:
+    out = np.zeros(19)
+    lib().orc19_teq(float(rho), _d(out))
+    return out
+
+
+def q19_cvec(F) -> np.ndarray:
+    out = np.zeros(19)
+    lib().orc19_cvec(_d(_vec3(F)), _d(out))
+    return out
+
+
+def q19_collide(f, F, s) -> np.ndarray:
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(19)
+    out = np.zeros(19)
+    assert lib().orc19_collide(_d(f), _d(_vec3(F)), _d(_rates(s)), _d(out)) == 0
+    return out
+
+
+def q19_equilibrium(rho, u) -> np.ndarray:
+    out = np.zeros(19)
+    assert lib().orc19_equilibrium(float(rho), _d(_vec3(u)), _d(out)) == 0
+    return out
+
+
 # --------------------------------------------------------------------------- lattice
-def init(geom: Geometry, rho0=None, u0=None) -> np.ndarray:
+LATTICES = ("d3q27", "d3q19")
+
+
+def _q(lattice: str) -> int:
+    if lattice not in LATTICES:
+        raise ValueError(f"lattice must be one of {LATTICES}")
+    return 27 if lattice == "d3q27" else 19
+
+
+def init(geom: Geometry, rho0=None, u0=None, lattice: str = "d3q27") -> np.ndarray:
     """f = f_eq(rho0, u0) at every node; rho0 (nz,ny,nx) or None (=1), u0 (3,nz,ny,nx) or None."""
-    f = np.zeros((27,) + geom.shape)
-    rc = lib().orc_init(geom.ptr(), _d(_f64(rho0)), _d(_f64(u0)), _d(f))
+    f = np.zeros((_q(lattice),) + geom.shape)
+    fn = lib().orc_init if lattice == "d3q27" else lib().orc19_init
+    rc = fn(geom.ptr(), _d(_f64(rho0)), _d(_f64(u0)), _d(f))
     assert rc == 0
     return f
 
 
-def step(geom: Geometry, f, s, force=(0.0, 0.0, 0.0), force_field=None, solid=None) -> np.ndarray:
+def step(geom: Geometry, f, s, force=(0.0, 0.0, 0.0), force_field=None, solid=None,
+         lattice: str = "d3q27") -> np.ndarray:
     """One time step (Steps 1-4); returns the pre-collision populations at t+1."""
     f = _f64(f)
+    assert f.shape[0] == _q(lattice)
     out = np.empty_like(f)
     solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
-    rc = lib().orc_step(geom.ptr(), _d(_rates(s)), _d(_vec3(force)), _d(_f64(force_field)), _u8(solid),
-                        _d(f), _d(out))
+    fn = lib().orc_step if lattice == "d3q27" else lib().orc19_step
+    rc = fn(geom.ptr(), _d(_rates(s)), _d(_vec3(force)), _d(_f64(force_field)), _u8(solid), _d(f), _d(out))
     assert rc == 0, rc
     return out
 
 
-def run(geom: Geometry, f, s, nsteps, force=(0.0, 0.0, 0.0), force_field=None, solid=None) -> np.ndarray:
+def run(geom: Geometry, f, s, nsteps, force=(0.0, 0.0, 0.0), force_field=None, solid=None,
+        lattice: str = "d3q27") -> np.ndarray:
     for _ in range(int(nsteps)):
-        f = step(geom, f, s, force, force_field, solid)
+        f = step(geom, f, s, force, force_field, solid, lattice)
     return f
 
 
-def macro(geom: Geometry, f, force=(0.0, 0.0, 0.0), force_field=None, solid=None):
+def macro(geom: Geometry, f, force=(0.0, 0.0, 0.0), force_field=None, solid=None, lattice: str = "d3q27"):
     """Eq. (9): returns (rho (nz,ny,nx), u (3,nz,ny,nx))."""
     f = _f64(f)
+    assert f.shape[0] == _q(lattice)
     rho = np.zeros(geom.shape)
     u = np.zeros((3,) + geom.shape)
     solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
-    rc = lib().orc_macro(geom.ptr(), _d(_vec3(force)), _d(_f64(force_field)), _u8(solid), _d(f), _d(rho), _d(u))
+    fn = lib().orc_macro if lattice == "d3q27" else lib().orc19_macro
+    rc = fn(geom.ptr(), _d(_vec3(force)), _d(_f64(force_field)), _u8(solid), _d(f), _d(rho), _d(u))
     assert rc == 0
     return rho, u
 

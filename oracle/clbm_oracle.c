@@ -718,3 +718,304 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* D3Q19 cascaded LBM of Appendix A                                          */
+/* ======================================================================== */
+/*
+ * The same scheme on the D3Q19 lattice: velocities of Eq. (A1), the 19 central
+ * moments of Eq. (A2) (its slot 9, printed as k~_020 a second time, read as
+ * k~_002 as for Eq. (12); M from the definition then equals the printed
+ * Eq. (A4), which a test checks), the block relaxation of Eq. (A3) with s3 for
+ * the six third-order moments and s4 for the three fourth-order ones, the
+ * equilibria of Eq. (A5) and the forcing terms of Eq. (A6).  Matrices are dense
+ * 19x19 and built entrywise; the step is Steps 1-4 of Sec. II B; streaming and
+ * bounce-back are those of the D3Q27 oracle above.  Rate array as above:
+ * {s0, s1, s2, s2b, s3, s3b, s4, s4b, s5, s6}; s3b, s4b, s5, s6 have no moment
+ * here and are ignored.
+ */
+#define Q19 19
+
+/* Eq. (A1) */
+static const int EX19[Q19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int EY19[Q19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int EZ19[Q19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+
+/* Eq. (A2): k000, k100, k010, k001, k110, k101, k011, k200, k020, k002, k120, k102,
+ * k210, k201, k012, k021, k220, k202, k022 */
+static const int PX19[Q19] = {0, 1, 0, 0, 1, 1, 0, 2, 0, 0, 1, 1, 2, 2, 0, 0, 2, 2, 0};
+static const int PY19[Q19] = {0, 0, 1, 0, 1, 0, 1, 0, 2, 0, 2, 0, 1, 0, 1, 2, 2, 0, 2};
+static const int PZ19[Q19] = {0, 0, 0, 1, 0, 1, 1, 0, 0, 2, 0, 2, 0, 1, 2, 1, 0, 2, 2};
+
+static int e19(int i, int axis) { return axis == 0 ? EX19[i] : (axis == 1 ? EY19[i] : EZ19[i]); }
+static int p19(int a, int axis) { return axis == 0 ? PX19[a] : (axis == 1 ? PY19[a] : PZ19[a]); }
+
+static void matvec19(const double *A, const double *x, double *y)
+{
+    for (int r = 0; r < Q19; ++r) {
+        double acc = 0.0;
+        for (int c = 0; c < Q19; ++c) acc += A[r * Q19 + c] * x[c];
+        y[r] = acc;
+    }
+}
+
+static int opposite19(int i)
+{
+    for (int j = 0; j < Q19; ++j)
+        if (EX19[j] == -EX19[i] && EY19[j] == -EY19[i] && EZ19[j] == -EZ19[i]) return j;
+    return -1;
+}
+
+/* Eq. (2) on D3Q19: K(u) = N(u) M, entry (a, i) = prod_alpha (e_i,alpha - u_alpha)^p_a,alpha */
+void orc19_matrix_K(const double *u, double *K)
+{
+    for (int a = 0; a < Q19; ++a)
+        for (int i = 0; i < Q19; ++i) {
+            double v = 1.0;
+            for (int ax = 0; ax < 3; ++ax) v *= ipow((double)e19(i, ax) - u[ax], p19(a, ax));
+            K[a * Q19 + i] = v;
+        }
+}
+
+/* Eq. (A4): raw moments k_mnp = <f | e_x^m e_y^n e_z^p> */
+void orc19_matrix_M(double *M)
+{
+    const double zero[3] = {0.0, 0.0, 0.0};
+    orc19_matrix_K(zero, M);
+}
+
+/* Shift matrix N(u) of the D3Q19 set, from the binomial expansion of (e - u)^p
+ * (every raw moment it needs is in the set: the set is closed under lowering
+ * exponents). */
+void orc19_matrix_N(const double *u, double *N)
+{
+    for (int a = 0; a < Q19; ++a)
+        for (int b = 0; b < Q19; ++b) {
+            double v = 1.0;
+            for (int ax = 0; ax < 3; ++ax) {
+                int pa = p19(a, ax), pb = p19(b, ax);
+                if (pb > pa) { v = 0.0; break; }
+                v *= binom(pa, pb) * ipow(-u[ax], pa - pb);
+            }
+            N[a * Q19 + b] = v;
+        }
+}
+
+int orc19_matrix_Minv(double *Minv)
+{
+    double M[Q19 * Q19];
+    orc19_matrix_M(M);
+    return invert(Q19, M, Minv);
+}
+
+/* Eq. (A3) */
+void orc19_matrix_S(const double *s, double *S)
+{
+    const double s0 = s[0], s1 = s[1], s2 = s[2], s2b = s[3], s3 = s[4], s4 = s[6];
+    const double sp = (s2b + 2.0 * s2) / 3.0, sm = (s2b - s2) / 3.0;
+    double diag[Q19] = {s0, s1, s1, s1, s2, s2, s2, 0, 0, 0, s3, s3, s3, s3, s3, s3, s4, s4, s4};
+    memset(S, 0, sizeof(double) * Q19 * Q19);
+    for (int a = 0; a < Q19; ++a) S[a * Q19 + a] = diag[a];
+    for (int r = 7; r <= 9; ++r)
+        for (int c = 7; c <= 9; ++c) S[r * Q19 + c] = (r == c) ? sp : sm;
+}
+
+/* Eq. (A5) */
+void orc19_teq(double rho, double *teq)
+{
+    memset(teq, 0, sizeof(double) * Q19);
+    teq[0] = rho;
+    teq[7] = teq[8] = teq[9] = rho * CS2;
+    teq[16] = teq[17] = teq[18] = rho * CS2 * CS2;
+}
+
+/* Eq. (A6) */
+void orc19_cvec(const double *F, double *C)
+{
+    const double Fx = F[0], Fy = F[1], Fz = F[2];
+    memset(C, 0, sizeof(double) * Q19);
+    C[1] = Fx;
+    C[2] = Fy;
+    C[3] = Fz;
+    C[10] = Fx * CS2;
+    C[11] = Fx * CS2;
+    C[12] = Fy * CS2;
+    C[13] = Fz * CS2;
+    C[14] = Fy * CS2;
+    C[15] = Fz * CS2;
+}
+
+void orc19_velocities(int *e)
+{
+    for (int i = 0; i < Q19; ++i) {
+        e[3 * i] = EX19[i];
+        e[3 * i + 1] = EY19[i];
+        e[3 * i + 2] = EZ19[i];
+    }
+}
+
+void orc19_exponents(int *p)
+{
+    for (int a = 0; a < Q19; ++a) {
+        p[3 * a] = PX19[a];
+        p[3 * a + 1] = PY19[a];
+        p[3 * a + 2] = PZ19[a];
+    }
+}
+
+static void macro_node19(const double *f, const double *F, double *rho, double *u)
+{
+    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int i = 0; i < Q19; ++i) {
+        r += f[i];
+        jx += f[i] * EX19[i];
+        jy += f[i] * EY19[i];
+        jz += f[i] * EZ19[i];
+    }
+    *rho = r;
+    u[0] = (jx + 0.5 * F[0]) / r;
+    u[1] = (jy + 0.5 * F[1]) / r;
+    u[2] = (jz + 0.5 * F[2]) / r;
+}
+
+typedef struct {
+    double S[Q19 * Q19];
+    double Minv[Q19 * Q19];
+} orc19_consts;
+
+static int consts19_init(orc19_consts *k, const double *s)
+{
+    orc19_matrix_S(s, k->S);
+    return orc19_matrix_Minv(k->Minv);
+}
+
+/* Steps 1-3 of Sec. II B on one D3Q19 node */
+static void collide_node19(const orc19_consts *k, const double *f, const double *F, double *fs)
+{
+    double rho, u[3], K[Q19 * Q19], Ninv[Q19 * Q19];
+    double T[Q19], Tt[Q19], teq[Q19], C[Q19], SA[Q19], SB[Q19], SC[Q19], Ts[Q19];
+    macro_node19(f, F, &rho, u);
+    orc19_matrix_K(u, K);
+    matvec19(K, f, Tt);
+    orc19_teq(rho, teq);
+    orc19_cvec(F, C);
+    matvec19(k->S, Tt, SA);
+    matvec19(k->S, teq, SB);
+    matvec19(k->S, C, SC);
+    for (int a = 0; a < Q19; ++a) Ts[a] = Tt[a] - SA[a] + SB[a] + C[a] - 0.5 * SC[a];
+    const double um[3] = {-u[0], -u[1], -u[2]}; /* N^-1(u) = N(-u) */
+    orc19_matrix_N(um, Ninv);
+    matvec19(Ninv, Ts, T);
+    matvec19(k->Minv, T, fs);
+}
+
+int orc19_collide(const double *f, const double *F, const double *s, double *fs)
+{
+    orc19_consts k;
+    if (consts19_init(&k, s)) return 1;
+    collide_node19(&k, f, F, fs);
+    return 0;
+}
+
+/* Generalised local equilibrium on D3Q19: f_eq = M^-1 N(-u) T_eq(rho) */
+int orc19_equilibrium(double rho, const double *u, double *feq)
+{
+    double Minv[Q19 * Q19], Ninv[Q19 * Q19], teq[Q19], T[Q19];
+    const double um[3] = {-u[0], -u[1], -u[2]};
+    if (orc19_matrix_Minv(Minv)) return 1;
+    orc19_teq(rho, teq);
+    orc19_matrix_N(um, Ninv);
+    matvec19(Ninv, teq, T);
+    matvec19(Minv, T, feq);
+    return 0;
+}
+
+/* One D3Q19 time step; arguments as orc_step, populations [19][n]. */
+int orc19_step(const int *geom, const double *s, const double *Fu, const double *Ff,
+               const uint8_t *solid, const double *fin, double *fout)
+{
+    orc_geom G;
+    orc19_consts k;
+    if (geom_read(geom, &G)) return 1;
+    if (consts19_init(&k, s)) return 2;
+    const long n = G.n;
+    for (long idx = 0; idx < (long)Q19 * n; ++idx) fout[idx] = NAN;
+    if (solid)
+        for (long node = 0; node < n; ++node)
+            if (solid[node])
+                for (int i = 0; i < Q19; ++i) fout[(long)i * n + node] = fin[(long)i * n + node];
+    int opp[Q19];
+    for (int i = 0; i < Q19; ++i) opp[i] = opposite19(i);
+
+#pragma omp parallel for schedule(static)
+    for (long node = 0; node < n; ++node) {
+        if (solid && solid[node]) continue;
+        const int x = (int)(node % G.w[0]);
+        const int y = (int)((node / G.w[0]) % G.w[1]);
+        const int z = (int)(node / ((long)G.w[0] * G.w[1]));
+        double f[Q19], fs[Q19], F[3];
+        for (int i = 0; i < Q19; ++i) f[i] = fin[(long)i * n + node];
+        force_at(Fu, Ff, n, node, F);
+        collide_node19(&k, f, F, fs);
+        for (int i = 0; i < Q19; ++i) {
+            const int lx = locate(&G, 0, G.o[0] + x + EX19[i]);
+            const int ly = locate(&G, 1, G.o[1] + y + EY19[i]);
+            const int lz = locate(&G, 2, G.o[2] + z + EZ19[i]);
+            if (lx == -2 || ly == -2 || lz == -2) continue;
+            long tgt = -1;
+            if (lx >= 0 && ly >= 0 && lz >= 0) {
+                tgt = (long)lx + (long)G.w[0] * ((long)ly + (long)G.w[1] * lz);
+                if (solid && solid[tgt]) tgt = -1;
+            }
+            if (tgt >= 0)
+                fout[(long)i * n + tgt] = fs[i];
+            else
+                fout[(long)opp[i] * n + node] = fs[i];
+        }
+    }
+    return 0;
+}
+
+/* Eq. (9) on every D3Q19 node. */
+int orc19_macro(const int *geom, const double *Fu, const double *Ff, const uint8_t *solid,
+                const double *f, double *rho, double *u)
+{
+    orc_geom G;
+    if (geom_read(geom, &G)) return 1;
+    const long n = G.n;
+#pragma omp parallel for schedule(static)
+    for (long node = 0; node < n; ++node) {
+        if (solid && solid[node]) {
+            rho[node] = 0.0;
+            u[node] = u[n + node] = u[2 * n + node] = 0.0;
+            continue;
+        }
+        double fl[Q19], F[3], r, uu[3];
+        for (int i = 0; i < Q19; ++i) fl[i] = f[(long)i * n + node];
+        force_at(Fu, Ff, n, node, F);
+        macro_node19(fl, F, &r, uu);
+        rho[node] = r;
+        u[node] = uu[0];
+        u[n + node] = uu[1];
+        u[2 * n + node] = uu[2];
+    }
+    return 0;
+}
+
+/* Initial D3Q19 state: f = f_eq(rho0(x), u0(x)). */
+int orc19_init(const int *geom, const double *rho0, const double *u0, double *f)
+{
+    orc_geom G;
+    if (geom_read(geom, &G)) return 1;
+    const long n = G.n;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long node = 0; node < n; ++node) {
+        double u[3], fe[Q19];
+        const double r = rho0 ? rho0[node] : 1.0;
+        for (int a = 0; a < 3; ++a) u[a] = u0 ? u0[(long)a * n + node] : 0.0;
+        bad |= orc19_equilibrium(r, u, fe);
+        for (int i = 0; i < Q19; ++i) f[(long)i * n + node] = fe[i];
+    }
+    return bad ? 2 : 0;
+}
