@@ -49,9 +49,9 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def bytes_per_node(storage: str, field: bool, solid: bool) -> int:
+def bytes_per_node(storage: str, field: bool, solid: bool, q: int = 27) -> int:
     size = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
-    b = 2 * 27 * size
+    b = 2 * q * size
     if field:
         b += 3 * (8 if storage == "f64" else 4)
     if solid:
@@ -261,6 +261,21 @@ def main():
                 lv.set_fused_steps(True)
                 variants[f"kolmogorov_{L}_{storage}"]["single_step_mlups"] = round(nodes / (ms1 * 1e-3) / 1e6, 1)
             log(f"[bench] {storage}: {ms:.3f} ms/step, {variants[f'kolmogorov_{L}_{storage}']}")
+            lv.close()
+            del lv
+            torch.cuda.empty_cache()
+        # the D3Q19 scheme of Appendix A on the same lattice and force field
+        for storage in ("f32", "f64", "f16"):
+            field = F32_dev if storage != "f64" else F64_dev
+            lv = Lattice(dims, (0, 0, 0), storage, rates, force_field=field, device=dev, lattice="d3q19")
+            lv.init(None, u0_dev)
+            lv.step(3)
+            ms = time_steps(torch, lv, 10)
+            b = bytes_per_node(storage, True, False, q=19)
+            key = f"kolmogorov_{L}_d3q19_{storage}"
+            variants[key] = {"mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4),
+                             "bytes_per_node": b, "frac": round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log(f"[bench] D3Q19 {storage}: {variants[key]}")
             lv.close()
             del lv
             torch.cuda.empty_cache()

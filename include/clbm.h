@@ -3,7 +3,7 @@
  * library: the collide-and-stream update of Fei, Luo & Li, "Three-dimensional
  * cascaded lattice Boltzmann method: improved implementation and consistent
  * forcing scheme" (arXiv:1801.04586), its adjoint, and reduced-precision
- * population storage.
+ * population storage; also the D3Q19 variant of the paper's Appendix A.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -15,7 +15,9 @@
  *    leaving fluid node x towards a wall or a solid node returns to x,
  *    reversed, one step later.  On a walled axis node j sits at coordinate
  *    j + 1/2 with walls at 0 and n.
- *  - Populations i = 0..26 follow the velocity order of Eq. (1).
+ *  - Populations i = 0..Q-1 follow the velocity order of Eq. (1) (Q = 27) or
+ *    of Eq. (A1) (Q = 19, lattice CLBM_D3Q19: the first 19 velocities of
+ *    Eq. (1)).
  *  - Pointers are device pointers unless a comment says "host".  Every device
  *    buffer is allocated and freed by the caller; the library never frees
  *    caller memory.  Buffers must be 16-byte aligned.
@@ -28,7 +30,7 @@
  *
  * State buffers
  * -------------
- * A state is one array [27][nz][ny][nx] of the storage type.  Its contents are
+ * A state is one array [Q][nz][ny][nx] of the storage type.  Its contents are
  * the populations in "pull" order: entry [i][y] holds the pre-collision
  * population f_i(y + e_i, t) when y + e_i is a fluid node, and f_opp(i)(y, t)
  * (the one that bounces back into y) when the link from y along e_i is
@@ -38,8 +40,8 @@
  * pre-collision populations f(x, t).  Storage types:
  *    CLBM_F64  stores f_i itself, arithmetic in FP64;
  *    CLBM_F32, CLBM_F16, CLBM_BF16 store the deviation f_i - w_i from the
- *    rest-state weights (8/27, 2/27, 1/54, 1/216), rounded to nearest even,
- *    arithmetic in FP32.
+ *    rest-state weights (D3Q27: 8/27, 2/27, 1/54, 1/216; D3Q19: 1/3, 1/18,
+ *    1/36), rounded to nearest even, arithmetic in FP32.
  * Entries belonging to solid nodes are never read; the step stores unspecified
  * values there (whole cache lines are written for speed).
  */
@@ -53,7 +55,17 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 1
+#define CLBM_ABI_VERSION 2
+
+/* Velocity sets: D3Q27 (Eq. (1), moment set Eq. (12)) and D3Q19 (Appendix A,
+ * Eq. (A1)-(A6): velocities without the eight corners, moments of Eq. (A2),
+ * rates s3 for the six third-order and s4 for the three fourth-order moments;
+ * s3b, s4b, s5 and s6 are unused).  D3Q19 has no adjoint (clbm_adjoint_step and
+ * clbm_loss_seed return CLBM_EINVAL) and never uses fused step pairs. */
+typedef enum clbm_lattice {
+    CLBM_D3Q27 = 0,
+    CLBM_D3Q19 = 1
+} clbm_lattice;
 
 typedef enum clbm_dtype {
     CLBM_F64 = 0,
@@ -77,7 +89,7 @@ typedef struct clbm_desc {
     int32_t nx, ny, nz;       /* >= 1 each, nx * ny * nz < 2^31 */
     int32_t wall[3];          /* per axis: 0 periodic, 1 half-way bounce-back walls */
     int32_t storage;          /* clbm_dtype */
-    int32_t reserved;         /* must be 0 */
+    int32_t lattice;          /* clbm_lattice: CLBM_D3Q27 (0) or CLBM_D3Q19 (1) */
     /* Relaxation rates of Eq. (13), in this order:
      * s0, s1, s2 (= s_nu, shear: nu = (1/s2 - 1/2)/3), s2b (bulk:
      * xi = 2/3 (1/s2b - 1/2)/3), s3, s3b, s4, s4b, s5, s6.  Each in (0, 2). */
@@ -165,17 +177,17 @@ int clbm_copy(clbm_ctx *ctx, const void *src, void *dst);
  * synchronises the stream and returns CLBM_ENONFINITE if n_bad > 0. */
 int clbm_moments(clbm_ctx *ctx, const void *state, double *rho, double *u, double *totals, int64_t *n_bad);
 
-/* Pre-collision populations f(x, t) of a state, as device FP64 [27][N] in
+/* Pre-collision populations f(x, t) of a state, as device FP64 [Q][N] in
  * Eq. (1) order (f itself, not the deviation).  Solid nodes get 0. */
 int clbm_get_populations(clbm_ctx *ctx, const void *state, double *f);
 
-/* Pre-collision populations of selected nodes: out (device FP64 [27][count])
+/* Pre-collision populations of selected nodes: out (device FP64 [Q][count])
  * gets f_i at node nodes[k] (device int32 [count], node ids as above) in
  * column k.  Solid nodes give 0; ids outside [0, N) give NaN.  count >= 0. */
 int clbm_sample_populations(clbm_ctx *ctx, const void *state, const int32_t *nodes, int32_t count, double *out);
 
 /* Inverse of clbm_get_populations: writes into `state` the buffer whose
- * pre-collision populations are f (device FP64 [27][N]); values are rounded to
+ * pre-collision populations are f (device FP64 [Q][N]); values are rounded to
  * the storage type.  Solid-node entries are left untouched. */
 int clbm_set_populations(clbm_ctx *ctx, const double *f, void *state);
 

@@ -23,6 +23,10 @@ STORAGE_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float1
 # arithmetic / adjoint / force-field type per storage
 REAL_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float32, "bf16": torch.float32}
 RATE_NAMES = ("s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6")
+ABI_VERSION = 2  # CLBM_ABI_VERSION of include/clbm.h
+CLBM_D3Q27, CLBM_D3Q19 = 0, 1
+LATTICE = {"d3q27": CLBM_D3Q27, "d3q19": CLBM_D3Q19}
+LATTICE_Q = {"d3q27": 27, "d3q19": 19}
 
 
 class ClbmError(RuntimeError):
@@ -38,7 +42,7 @@ class Desc(ctypes.Structure):
         ("nz", ctypes.c_int32),
         ("wall", ctypes.c_int32 * 3),
         ("storage", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("lattice", ctypes.c_int32),
         ("s", ctypes.c_double * 10),
         ("force_uniform", ctypes.c_double * 3),
         ("force_scale", ctypes.c_double),
@@ -84,7 +88,7 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = res
-    if L.clbm_abi_version() != 1:
+    if L.clbm_abi_version() != ABI_VERSION:
         raise ImportError("libclbm.so ABI version mismatch")
     _lib = L
     return L
@@ -196,13 +200,13 @@ class Context:
 
 
 def make_desc(dims, walls=(0, 0, 0), storage="f32", rates=None, force=(0.0, 0.0, 0.0), force_field=None,
-              force_scale=1.0, solid=None) -> Desc:
+              force_scale=1.0, solid=None, lattice="d3q27") -> Desc:
     d = Desc()
     d.nx, d.ny, d.nz = (int(v) for v in dims)
     for a in range(3):
         d.wall[a] = int(walls[a])
     d.storage = STORAGE[storage]
-    d.reserved = 0
+    d.lattice = LATTICE[lattice]
     rates = [1.0] * 10 if rates is None else [float(v) for v in rates]
     for k in range(10):
         d.s[k] = rates[k]
@@ -225,16 +229,17 @@ def _dev_tensor(a, dtype, device, shape=None) -> Optional[torch.Tensor]:
 
 
 class Lattice:
-    """A D3Q27 cascaded-LBM lattice on one GPU: two state buffers and a context.
+    """A cascaded-LBM lattice on one GPU: two state buffers and a context.
 
     dims = (nx, ny, nz); walls per axis (0 periodic, 1 half-way bounce-back);
     storage in {"f64", "f32", "f16", "bf16"}; rates = the 10 rates of Eq. (13);
     force = uniform force density; force_field = (3, nz, ny, nx) field added to
-    it (times force_scale); solid = (nz, ny, nx) mask, nonzero = solid.
+    it (times force_scale); solid = (nz, ny, nx) mask, nonzero = solid;
+    lattice = "d3q27" (Eq. (1)) or "d3q19" (Appendix A).
     """
 
     def __init__(self, dims: Sequence[int], walls=(0, 0, 0), storage="f32", rates=None, force=(0.0, 0.0, 0.0),
-                 force_field=None, force_scale=1.0, solid=None, device=None):
+                 force_field=None, force_scale=1.0, solid=None, device=None, lattice="d3q27"):
         if not torch.cuda.is_available():
             raise RuntimeError("clbm needs a GPU (HIP); none is visible")
         self.device = torch.device(device if device is not None else "cuda")
@@ -244,6 +249,8 @@ class Lattice:
         self.n = nx * ny * nz
         self.walls = tuple(int(w) for w in walls)
         self.storage = storage
+        self.lattice = lattice
+        self.q = LATTICE_Q[lattice]
         self.real = REAL_TORCH[storage]
         self.force_field = _dev_tensor(force_field, self.real, self.device, (3,) + self.shape)
         self.solid = _dev_tensor(solid, torch.uint8, self.device, self.shape)
@@ -251,9 +258,9 @@ class Lattice:
         self.force = tuple(float(v) for v in force)
         self.force_scale = float(force_scale)
         desc = make_desc(self.dims, self.walls, storage, self.rates, self.force, self.force_field, force_scale,
-                         self.solid)
+                         self.solid, lattice)
         self.ctx = Context(desc, self.device)
-        self.bufs = [torch.empty((27,) + self.shape, dtype=STORAGE_TORCH[storage], device=self.device)
+        self.bufs = [torch.empty((self.q,) + self.shape, dtype=STORAGE_TORCH[storage], device=self.device)
                      for _ in range(2)]
         self.cur = 0
         self.t = 0
@@ -291,8 +298,8 @@ class Lattice:
     @property
     def uses_fused_pairs(self) -> bool:
         """Whether step(n) runs pairs of steps as one fused launch (the rule of clbm_run)."""
-        return (getattr(self, "_fused", True) and self.storage == "f32" and self.walls == (0, 0, 0)
-                and self.solid is None)
+        return (getattr(self, "_fused", True) and self.lattice == "d3q27" and self.storage == "f32"
+                and self.walls == (0, 0, 0) and self.solid is None)
 
     def set_rates(self, rates):
         self.rates = np.asarray(rates, dtype=np.float64)
@@ -304,6 +311,11 @@ class Lattice:
         self.force_scale = float(force_scale)
         self.ctx.set_force(self.force, self.force_field, self.force_scale)
 
+    def set_force_scale(self, scale: float):
+        """Rescale the per-node force field (time-dependent forcing, F(t) at the collision of step t)."""
+        self.force_scale = float(scale)
+        self.ctx.set_force(self.force, self.force_field, self.force_scale)
+
     # ---- observables
     def moments(self, fields: bool = True):
         """Returns (rho (nz,ny,nx) f64, u (3,nz,ny,nx) f64, totals [mass, px, py, pz], n_bad)."""
@@ -313,20 +325,20 @@ class Lattice:
         return rho, u, totals, nbad
 
     def populations(self) -> torch.Tensor:
-        """Pre-collision populations f(x, t) as f64 (27, nz, ny, nx), Eq. (1) order."""
-        out = torch.empty((27,) + self.shape, dtype=torch.float64, device=self.device)
+        """Pre-collision populations f(x, t) as f64 (Q, nz, ny, nx), Eq. (1) / (A1) order."""
+        out = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
         self.ctx.get_populations(self.state, out)
         return out
 
     def set_populations(self, f):
-        ft = _dev_tensor(f, torch.float64, self.device, (27,) + self.shape)
+        ft = _dev_tensor(f, torch.float64, self.device, (self.q,) + self.shape)
         self.ctx.set_populations(ft, self.state)
 
     def sample(self, xyz) -> np.ndarray:
-        """Pre-collision populations (27, k) f64 at the nodes xyz = [(x, y, z), ...]."""
+        """Pre-collision populations (Q, k) f64 at the nodes xyz = [(x, y, z), ...]."""
         nx, ny, _ = self.dims
         ids = torch.tensor([x + nx * (y + ny * z) for x, y, z in xyz], dtype=torch.int32, device=self.device)
-        out = torch.empty((27, len(xyz)), dtype=torch.float64, device=self.device)
+        out = torch.empty((self.q, len(xyz)), dtype=torch.float64, device=self.device)
         self.ctx.sample_populations(self.state, ids, out)
         return out.cpu().numpy()
 

@@ -1,6 +1,6 @@
 // Host side of the C ABI declared in include/clbm.h: argument validation,
-// launch geometry, variant dispatch and FP64 reductions for the D3Q27 cascaded
-// LBM kernels in kernels.hpp.
+// launch geometry, variant dispatch and FP64 reductions for the D3Q27 (and
+// D3Q19) cascaded LBM kernels in kernels.hpp.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -75,7 +75,7 @@ int validate_desc(const clbm_desc *d)
     for (int a = 0; a < 3; ++a)
         if (d->wall[a] != 0 && d->wall[a] != 1) return fail(nullptr, CLBM_EINVAL, "wall flags must be 0 or 1");
     if (d->storage < CLBM_F64 || d->storage > CLBM_BF16) return fail(nullptr, CLBM_EDTYPE, "unknown storage type");
-    if (d->reserved != 0) return fail(nullptr, CLBM_EINVAL, "reserved field must be 0");
+    if (d->lattice != CLBM_D3Q27 && d->lattice != CLBM_D3Q19) return fail(nullptr, CLBM_EINVAL, "unknown lattice");
     int rc = validate_rates(nullptr, d->s);
     if (rc) return rc;
     for (int a = 0; a < 3; ++a)
@@ -86,6 +86,7 @@ int validate_desc(const clbm_desc *d)
 }
 
 size_t store_size(int storage) { return storage == CLBM_F64 ? 8 : (storage == CLBM_F32 ? 4 : 2); }
+int lattice_q(const clbm_desc &d) { return d.lattice == CLBM_D3Q19 ? 19 : 27; }
 
 template <typename R>
 Rates<R> make_rates(const double *s)
@@ -108,34 +109,50 @@ Forcing<R> make_forcing(const clbm_desc &d)
     return f;
 }
 
-// Compile-time variant of the kernels: storage type and which boundary/force code is needed.
-template <typename S, bool C, bool So, bool Fi>
+// Compile-time variant of the kernels: storage type, which boundary/force code is
+// needed, and the lattice (27 or 19 velocities).
+template <typename S, bool C, bool So, bool Fi, int Qv>
 struct V {
     using Store = S;
     using R = typename Traits<S>::R;
     static constexpr bool check = C, solid = So, field = Fi;
+    static constexpr int q = Qv;
 };
 
-template <typename S, typename F>
+template <typename S, int Qv, typename F>
 int dispatch_flags(const clbm_ctx *c, F &&f)
 {
     const bool solid = c->links != nullptr;
     const bool check = solid || c->d.wall[0] || c->d.wall[1] || c->d.wall[2];
     const bool field = c->d.force != nullptr;
-    if (solid) return field ? f(V<S, true, true, true>{}) : f(V<S, true, true, false>{});
-    if (check) return field ? f(V<S, true, false, true>{}) : f(V<S, true, false, false>{});
-    return field ? f(V<S, false, false, true>{}) : f(V<S, false, false, false>{});
+    if (solid) return field ? f(V<S, true, true, true, Qv>{}) : f(V<S, true, true, false, Qv>{});
+    if (check) return field ? f(V<S, true, false, true, Qv>{}) : f(V<S, true, false, false, Qv>{});
+    return field ? f(V<S, false, false, true, Qv>{}) : f(V<S, false, false, false, Qv>{});
+}
+
+template <int Qv, typename F>
+int dispatch_storage(const clbm_ctx *c, F &&f)
+{
+    switch (c->d.storage) {
+    case CLBM_F64: return dispatch_flags<double, Qv>(c, f);
+    case CLBM_F32: return dispatch_flags<float, Qv>(c, f);
+    case CLBM_F16: return dispatch_flags<_Float16, Qv>(c, f);
+    default: return dispatch_flags<__bf16, Qv>(c, f);
+    }
 }
 
 template <typename F>
 int dispatch(const clbm_ctx *c, F &&f)
 {
-    switch (c->d.storage) {
-    case CLBM_F64: return dispatch_flags<double>(c, f);
-    case CLBM_F32: return dispatch_flags<float>(c, f);
-    case CLBM_F16: return dispatch_flags<_Float16>(c, f);
-    default: return dispatch_flags<__bf16>(c, f);
-    }
+    return c->d.lattice == CLBM_D3Q19 ? dispatch_storage<19>(c, f) : dispatch_storage<27>(c, f);
+}
+
+// The adjoint and the loss exist for D3Q27 only.
+template <typename F>
+int dispatch_d3q27(clbm_ctx *c, F &&f)
+{
+    if (c->d.lattice != CLBM_D3Q27) return fail(c, CLBM_EINVAL, "the adjoint needs the D3Q27 lattice");
+    return dispatch_storage<27>(c, f);
 }
 
 unsigned node_blocks(const clbm_ctx *c) { return static_cast<unsigned>((c->nodes + kBlock - 1) / kBlock); }
@@ -163,12 +180,17 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
         using R = typename Vt::R;
         auto go = [&](auto h) {
             constexpr bool H = decltype(h)::value;
-            hipLaunchKernelGGL((k_step<S, Vt::check, Vt::solid, Vt::field, H>), dim3(node_blocks(c)), dim3(kBlock),
-                               0, c->stream, static_cast<const S *>(src), static_cast<S *>(dst), c->geom, c->links,
-                               static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
+            hipLaunchKernelGGL((k_step<S, Vt::check, Vt::solid, Vt::field, H, Vt::q>), dim3(node_blocks(c)),
+                               dim3(kBlock), 0, c->stream, static_cast<const S *>(src), static_cast<S *>(dst), c->geom,
+                               c->links, static_cast<const R *>(c->d.force), make_forcing<R>(c->d),
+                               make_rates<R>(c->d.s));
             return check_launch(c, "step kernel launch");
         };
-        return high1 ? go(std::true_type{}) : go(std::false_type{});
+        // D3Q19 always takes the general collision
+        if constexpr (Vt::q == 27)
+            return high1 ? go(std::true_type{}) : go(std::false_type{});
+        else
+            return go(std::false_type{});
     });
 }
 
@@ -178,8 +200,8 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
 // kernel's cost per step is set by its arithmetic and barriers, not by memory.
 bool fused_pairs(const clbm_ctx *c)
 {
-    return !(c->options & CLBM_OPT_SINGLE_STEP) && c->d.storage == CLBM_F32 && !c->links && !c->d.wall[0] &&
-           !c->d.wall[1] && !c->d.wall[2];
+    return !(c->options & CLBM_OPT_SINGLE_STEP) && c->d.lattice == CLBM_D3Q27 && c->d.storage == CLBM_F32 &&
+           !c->links && !c->d.wall[0] && !c->d.wall[1] && !c->d.wall[2];
 }
 
 int launch_step2(clbm_ctx *c, const void *src, void *dst)
@@ -273,7 +295,12 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
     if (desc->solid) {
         e = hipMalloc(&c->links, sizeof(uint32_t) * c->nodes);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_links, dim3(node_blocks(c)), dim3(kBlock), 0, c->stream, c->geom, desc->solid, c->links);
+            if (desc->lattice == CLBM_D3Q19)
+                hipLaunchKernelGGL(k_links<19>, dim3(node_blocks(c)), dim3(kBlock), 0, c->stream, c->geom, desc->solid,
+                                   c->links);
+            else
+                hipLaunchKernelGGL(k_links<27>, dim3(node_blocks(c)), dim3(kBlock), 0, c->stream, c->geom, desc->solid,
+                                   c->links);
             e = hipGetLastError();
         }
         if (e != hipSuccess) {
@@ -343,7 +370,7 @@ int clbm_init(clbm_ctx *ctx, void *state, const double *rho0, const double *u0)
     return dispatch(ctx, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
-        hipLaunchKernelGGL((k_init<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0, ctx->stream,
+        hipLaunchKernelGGL((k_init<S, Vt::check, Vt::solid, Vt::q>), dim3(node_blocks(ctx)), dim3(kBlock), 0, ctx->stream,
                            static_cast<S *>(state), ctx->geom, ctx->links, rho0, u0);
         return check_launch(ctx, "init kernel launch");
     });
@@ -396,7 +423,7 @@ int clbm_copy(clbm_ctx *ctx, const void *src, void *dst)
     if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
     if (!src || !dst || !aligned(src) || !aligned(dst) || src == dst)
         return fail(ctx, CLBM_EINVAL, "bad copy buffers");
-    const size_t bytes = ctx->nodes * 27 * store_size(ctx->d.storage);
+    const size_t bytes = ctx->nodes * lattice_q(ctx->d) * store_size(ctx->d.storage);
     const size_t n16 = bytes / 16, tail = bytes % 16;
     if (n16) {
         size_t blocks = (n16 + kBlock - 1) / kBlock;
@@ -424,7 +451,7 @@ int clbm_moments(clbm_ctx *ctx, const void *state, double *rho, double *u, doubl
         using Vt = decltype(v);
         using S = typename Vt::Store;
         using R = typename Vt::R;
-        hipLaunchKernelGGL((k_moments<S, Vt::check, Vt::solid, Vt::field>), dim3(nb), dim3(kBlock), 0, ctx->stream,
+        hipLaunchKernelGGL((k_moments<S, Vt::check, Vt::solid, Vt::field, Vt::q>), dim3(nb), dim3(kBlock), 0, ctx->stream,
                            static_cast<const S *>(state), ctx->geom, ctx->links, static_cast<const R *>(ctx->d.force),
                            make_forcing<R>(ctx->d), rho, u, ctx->partials);
         return check_launch(ctx, "moments kernel launch");
@@ -456,7 +483,7 @@ int clbm_get_populations(clbm_ctx *ctx, const void *state, double *f)
     return dispatch(ctx, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
-        hipLaunchKernelGGL((k_get_populations<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
+        hipLaunchKernelGGL((k_get_populations<S, Vt::check, Vt::solid, Vt::q>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
                            ctx->stream, static_cast<const S *>(state), ctx->geom, ctx->links, f);
         return check_launch(ctx, "get_populations kernel launch");
     });
@@ -473,7 +500,7 @@ int clbm_sample_populations(clbm_ctx *ctx, const void *state, const int32_t *nod
         using Vt = decltype(v);
         using S = typename Vt::Store;
         const unsigned blocks = static_cast<unsigned>((count + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL((k_sample_populations<S, Vt::check, Vt::solid>), dim3(blocks), dim3(kBlock), 0,
+        hipLaunchKernelGGL((k_sample_populations<S, Vt::check, Vt::solid, Vt::q>), dim3(blocks), dim3(kBlock), 0,
                            ctx->stream, static_cast<const S *>(state), ctx->geom, ctx->links, nodes,
                            static_cast<uint32_t>(count), out);
         return check_launch(ctx, "sample_populations kernel launch");
@@ -487,7 +514,7 @@ int clbm_set_populations(clbm_ctx *ctx, const double *f, void *state)
     return dispatch(ctx, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
-        hipLaunchKernelGGL((k_set_populations<S, Vt::check, Vt::solid>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
+        hipLaunchKernelGGL((k_set_populations<S, Vt::check, Vt::solid, Vt::q>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
                            ctx->stream, f, ctx->geom, ctx->links, static_cast<S *>(state));
         return check_launch(ctx, "set_populations kernel launch");
     });
@@ -502,7 +529,7 @@ int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, 
     if (lam_next == lam_out) return fail(ctx, CLBM_EINVAL, "lam_next and lam_out must be distinct");
     if ((dJdF && !aligned(dJdF)) || (dJds && !aligned(dJds))) return fail(ctx, CLBM_EINVAL, "dJdF/dJds misaligned");
     const unsigned nb = stride_blocks(ctx);
-    int rc = dispatch(ctx, [&](auto v) {
+    int rc = dispatch_d3q27(ctx, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
         using R = typename Vt::R;
@@ -527,7 +554,7 @@ int clbm_loss_seed(clbm_ctx *ctx, const void *state, const void *u_target, void 
     if ((dJdF && !aligned(dJdF)) || (J && (reinterpret_cast<uintptr_t>(J) & 7u)))
         return fail(ctx, CLBM_EINVAL, "dJdF/J misaligned");
     const unsigned nb = stride_blocks(ctx);
-    int rc = dispatch(ctx, [&](auto v) {
+    int rc = dispatch_d3q27(ctx, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
         using R = typename Vt::R;

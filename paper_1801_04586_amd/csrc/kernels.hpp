@@ -164,7 +164,7 @@ __device__ __forceinline__ void store_at(T *__restrict__ base, uint32_t byte_off
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
-template <typename S, bool CHECK, bool SOLID, bool REV, typename R>
+template <typename S, bool CHECK, bool SOLID, bool REV, int Q, typename R>
 __device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
                                              uint32_t lm, R (&v)[27]);
 
@@ -172,29 +172,37 @@ __device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t
 // (the stored value, deviation or not).  REV gathers along +e instead (adjoint).
 // With walls or solids, a wavefront whose nodes all have their 26 links open
 // (the common case) takes the unchecked path; only wavefronts touching a wall or
-// a solid test every link.
-constexpr uint32_t kAllLinks = (1u << 27) - 1u;
+// a solid test every link.  Lattice Q (27 or 19): slots without a population
+// (the D3Q19 corners) read nothing and hold 0.
+template <int Q>
+__host__ __device__ constexpr uint32_t all_links()
+{
+    uint32_t m = 0;
+    for (int t = 0; t < 27; ++t)
+        if (has_slot<Q>(t)) m |= 1u << t;
+    return m;
+}
 
-template <typename S, bool CHECK, bool SOLID, bool REV, typename R>
+template <typename S, bool CHECK, bool SOLID, bool REV, int Q = 27, typename R>
 __device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb, uint32_t lm,
                                        R (&v)[27])
 {
     if constexpr (CHECK) {
         bool open;
         if constexpr (SOLID)
-            open = lm == kAllLinks;
+            open = lm == all_links<Q>();
         else
             open = nb.vx[0] && nb.vx[2] && nb.vy[0] && nb.vy[2] && nb.vz[0] && nb.vz[2];
         if (__all(open))
-            gather_links<S, false, false, REV>(buf, N, n, nb, lm, v);
+            gather_links<S, false, false, REV, Q>(buf, N, n, nb, lm, v);
         else
-            gather_links<S, true, SOLID, REV>(buf, N, n, nb, lm, v);
+            gather_links<S, true, SOLID, REV, Q>(buf, N, n, nb, lm, v);
     } else {
-        gather_links<S, false, false, REV>(buf, N, n, nb, lm, v);
+        gather_links<S, false, false, REV, Q>(buf, N, n, nb, lm, v);
     }
 }
 
-template <typename S, bool CHECK, bool SOLID, bool REV, typename R>
+template <typename S, bool CHECK, bool SOLID, bool REV, int Q, typename R>
 __device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
                                              uint32_t lm, R (&v)[27])
 {
@@ -203,7 +211,9 @@ __device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t
         constexpr int t = decltype(TT)::value;
         constexpr int i = pop_of_slot(t);
         const S *__restrict__ Pi = buf + static_cast<size_t>(i) * N;
-        if constexpr (t == 13) {
+        if constexpr (!has_slot<Q>(t)) {
+            v[t] = R(0);
+        } else if constexpr (t == 13) {
             v[t] = static_cast<R>(to_real(load_at(Pi, n * es)));
         } else {
             uint32_t off;
@@ -224,7 +234,7 @@ __device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t
 }
 
 // Inverse of gather: write the value of slot t of node n where gather() reads it.
-template <typename S, bool CHECK, bool SOLID, typename R>
+template <typename S, bool CHECK, bool SOLID, int Q, typename R>
 __device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb, uint32_t lm,
                                         const R (&v)[27])
 {
@@ -233,7 +243,9 @@ __device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_
         constexpr int i = pop_of_slot(t);
         S *__restrict__ Pi = buf + static_cast<size_t>(i) * N;
         const S val = to_store<S>(v[t]);
-        if constexpr (t == 13) {
+        if constexpr (!has_slot<Q>(t)) {
+            // no population in this slot
+        } else if constexpr (t == 13) {
             Pi[n] = val;
         } else {
             uint32_t off;
@@ -253,6 +265,7 @@ __device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_
 // slot t into node n is open (the neighbour n - e exists and is fluid) and bit 13
 // (the rest population) set for every fluid node; solid nodes get 0.  One
 // coalesced 32-bit load per node then replaces 26 dependent mask loads.
+template <int Q>
 __global__ __launch_bounds__(kBlock) void k_links(Geom g, const uint8_t *__restrict__ solid, uint32_t *__restrict__ links)
 {
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
@@ -263,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_links(Geom g, const uint8_t *__restr
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         uint32_t off;
-        if (link_open<t, false, false>(nb, 0u, off) && solid[off] == 0) m |= 1u << t;
+        if (has_slot<Q>(t) && link_open<t, false, false>(nb, 0u, off) && solid[off] == 0) m |= 1u << t;
     });
     links[n] = solid[n] ? 0u : (m | (1u << 13));
 }
@@ -323,10 +336,25 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
 
 // ------------------------------------------------------------------ forward step
 // Steps 1-3 of Sec. II B on one node's deviations d = f - w (in place, registers).
-// HIGH1: every rate above second order is one (collide_high1).
-template <bool HIGH1 = false, typename R>
+// HIGH1: every rate above second order is one (collide_high1).  Q = 19: the D3Q19
+// scheme of Appendix A on the same slots (corner slots hold 0 on entry and exit).
+template <bool HIGH1 = false, int Q = 27, typename R>
 __device__ __forceinline__ void node_update(R (&v)[27], R Fx, R Fy, R Fz, const Rates<R> &rt)
 {
+    if constexpr (Q == 19) {
+        static_assert(!HIGH1, "D3Q19 uses the general collision");
+        raw_moments(v);
+        const R drho = v[slot(0, 0, 0)];
+        const R inv_rho = R(1) / (R(1) + drho);
+        const R ux = (v[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho;
+        const R uy = (v[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho;
+        const R uz = (v[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho;
+        central_shift(v, ux, uy, uz);
+        const AxisU<R> X(ux), Y(uy), Z(uz);
+        collide(v, drho, X, Y, Z, Fx, Fy, Fz, rt);  // Eq. (A3), (A5), (A6) on the moments of Eq. (A2)
+        reconstruct_q19(v, ux, uy, uz);
+        return;
+    }
     if constexpr (HIGH1) {
         R ux, uy, uz;
         collide_high1(v, Fx, Fy, Fz, rt, ux, uy, uz);
@@ -350,7 +378,7 @@ __device__ __forceinline__ void node_update(R (&v)[27], R Fx, R Fy, R Fz, const 
 // stores its (never read) entries, so that every wavefront writes whole cache
 // lines: lanes that skipped their stores would leave partially written lines,
 // which cost far more memory time than the extra bytes.
-template <typename S, bool CHECK, bool SOLID, bool FIELD, bool HIGH1>
+template <typename S, bool CHECK, bool SOLID, bool FIELD, bool HIGH1, int Q>
 __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src, S *__restrict__ dst, const Geom &g,
                                           const uint32_t *__restrict__ links,
                                           const typename Traits<S>::R *__restrict__ field,
@@ -365,33 +393,35 @@ __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src,
     neighbours(g, n, nb);
     R v[27];
     if (!SOLID || lm != 0u) {
-        gather<S, CHECK, SOLID, false>(src, g.N, n, nb, lm, v);
+        gather<S, CHECK, SOLID, false, Q>(src, g.N, n, nb, lm, v);
         if constexpr (!Traits<S>::kDev)
-            sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
+            sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= lattice_weight<Q, R>(decltype(T)::value); });
     } else {
         sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });
     }
 
     R Fx, Fy, Fz;
     force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
-    node_update<HIGH1>(v, Fx, Fy, Fz, rt);
+    node_update<HIGH1, Q>(v, Fx, Fy, Fz, rt);
 
     const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
-        R val = v[t];
-        if constexpr (!Traits<S>::kDev) val += weight_of_slot<R>(t);
-        store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.N, nb_off, to_store<S>(val));
+        if constexpr (has_slot<Q>(t)) {
+            R val = v[t];
+            if constexpr (!Traits<S>::kDev) val += lattice_weight<Q, R>(t);
+            store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.N, nb_off, to_store<S>(val));
+        }
     });
 }
 
-template <typename S, bool CHECK, bool SOLID, bool FIELD, bool HIGH1>
+template <typename S, bool CHECK, bool SOLID, bool FIELD, bool HIGH1, int Q>
 __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *__restrict__ dst, Geom g,
                                                  const uint32_t *__restrict__ links,
                                                  const typename Traits<S>::R *__restrict__ field,
                                                  Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
 {
-    step_node<S, CHECK, SOLID, FIELD, HIGH1>(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x, src, dst, g, links,
+    step_node<S, CHECK, SOLID, FIELD, HIGH1, Q>(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x, src, dst, g, links,
                                       field, fo, rt);
 }
 
@@ -572,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ pa
 // ------------------------------------------------------------------ macroscopic fields (Eq. (9))
 constexpr int kMomComp = 5;  // mass, momentum x/y/z, count of bad nodes
 
-template <typename S, bool CHECK, bool SOLID, bool FIELD>
+template <typename S, bool CHECK, bool SOLID, bool FIELD, int Q>
 __global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, Geom g,
                                                     const uint32_t *__restrict__ links,
                                                     const typename Traits<S>::R *__restrict__ field,
@@ -591,9 +621,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, G
         Nbr nb;
         neighbours(g, n, nb);
         double v[27];
-        gather<S, CHECK, SOLID, false>(src, g.N, n, nb, lm, v);
+        gather<S, CHECK, SOLID, false, Q>(src, g.N, n, nb, lm, v);
         if constexpr (!Traits<S>::kDev)
-            sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<double>(decltype(T)::value); });
+            sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= lattice_weight<Q, double>(decltype(T)::value); });
         raw_moments(v);
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
@@ -619,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, G
 }
 
 // ------------------------------------------------------------------ populations in/out, initial state
-template <typename S, bool CHECK, bool SOLID>
+template <typename S, bool CHECK, bool SOLID, int Q>
 __global__ __launch_bounds__(kBlock) void k_get_populations(const S *__restrict__ src, Geom g,
                                                             const uint32_t *__restrict__ links,
                                                             double *__restrict__ f)
@@ -628,23 +658,25 @@ __global__ __launch_bounds__(kBlock) void k_get_populations(const S *__restrict_
     if (n >= g.N) return;
     const uint32_t lm = SOLID ? links[n] : 0u;
     if (SOLID && lm == 0u) {
-        for (int i = 0; i < 27; ++i) f[static_cast<size_t>(i) * g.N + n] = 0.0;
+        for (int i = 0; i < Q; ++i) f[static_cast<size_t>(i) * g.N + n] = 0.0;
         return;
     }
     Nbr nb;
     neighbours(g, n, nb);
     double v[27];
-    gather<S, CHECK, SOLID, false>(src, g.N, n, nb, lm, v);
+    gather<S, CHECK, SOLID, false, Q>(src, g.N, n, nb, lm, v);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
-        double val = v[t];
-        if constexpr (Traits<S>::kDev) val += weight_of_slot<double>(t);
-        f[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = val;
+        if constexpr (has_slot<Q>(t)) {
+            double val = v[t];
+            if constexpr (Traits<S>::kDev) val += lattice_weight<Q, double>(t);
+            f[static_cast<size_t>(pop_of_slot(t)) * g.N + n] = val;
+        }
     });
 }
 
 // Pre-collision populations of `count` listed nodes: out[i][k] for node nodes[k].
-template <typename S, bool CHECK, bool SOLID>
+template <typename S, bool CHECK, bool SOLID, int Q>
 __global__ __launch_bounds__(kBlock) void k_sample_populations(const S *__restrict__ src, Geom g,
                                                                const uint32_t *__restrict__ links,
                                                                const int32_t *__restrict__ nodes, uint32_t count,
@@ -657,22 +689,24 @@ __global__ __launch_bounds__(kBlock) void k_sample_populations(const S *__restri
     const uint32_t n = valid ? static_cast<uint32_t>(id) : 0u;
     const uint32_t lm = SOLID ? links[n] : 0u;
     if (!valid || (SOLID && lm == 0u)) {
-        for (int i = 0; i < 27; ++i) out[static_cast<size_t>(i) * count + k] = valid ? 0.0 : NAN;
+        for (int i = 0; i < Q; ++i) out[static_cast<size_t>(i) * count + k] = valid ? 0.0 : NAN;
         return;
     }
     Nbr nb;
     neighbours(g, n, nb);
     double v[27];
-    gather<S, CHECK, SOLID, false>(src, g.N, n, nb, lm, v);
+    gather<S, CHECK, SOLID, false, Q>(src, g.N, n, nb, lm, v);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
-        double val = v[t];
-        if constexpr (Traits<S>::kDev) val += weight_of_slot<double>(t);
-        out[static_cast<size_t>(pop_of_slot(t)) * count + k] = val;
+        if constexpr (has_slot<Q>(t)) {
+            double val = v[t];
+            if constexpr (Traits<S>::kDev) val += lattice_weight<Q, double>(t);
+            out[static_cast<size_t>(pop_of_slot(t)) * count + k] = val;
+        }
     });
 }
 
-template <typename S, bool CHECK, bool SOLID>
+template <typename S, bool CHECK, bool SOLID, int Q>
 __global__ __launch_bounds__(kBlock) void k_set_populations(const double *__restrict__ f, Geom g,
                                                             const uint32_t *__restrict__ links, S *__restrict__ dst)
 {
@@ -685,16 +719,20 @@ __global__ __launch_bounds__(kBlock) void k_set_populations(const double *__rest
     double v[27];
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
-        double val = f[static_cast<size_t>(pop_of_slot(t)) * g.N + n];
-        if constexpr (Traits<S>::kDev) val -= weight_of_slot<double>(t);
-        v[t] = val;
+        if constexpr (has_slot<Q>(t)) {
+            double val = f[static_cast<size_t>(pop_of_slot(t)) * g.N + n];
+            if constexpr (Traits<S>::kDev) val -= lattice_weight<Q, double>(t);
+            v[t] = val;
+        } else {
+            v[t] = 0.0;
+        }
     });
-    scatter<S, CHECK, SOLID>(dst, g.N, n, nb, lm, v);
+    scatter<S, CHECK, SOLID, Q>(dst, g.N, n, nb, lm, v);
 }
 
 // f = f_eq(rho0, u0): the generalized equilibrium (NM)^-1 T_eq, computed in FP64
 // as the reconstruction of T_eq - N(u) M w.
-template <typename S, bool CHECK, bool SOLID>
+template <typename S, bool CHECK, bool SOLID, int Q>
 __global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, const uint32_t *__restrict__ links,
                                                  const double *__restrict__ rho0, const double *__restrict__ u0)
 {
@@ -711,10 +749,13 @@ __global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, co
     const AxisU<double> X(ux), Y(uy), Z(uz);
     double v[27];
     equilibrium_moments(v, drho, X, Y, Z);
-    reconstruct(v, ux, uy, uz);
+    if constexpr (Q == 19)
+        reconstruct_q19(v, ux, uy, uz);
+    else
+        reconstruct(v, ux, uy, uz);
     if constexpr (!Traits<S>::kDev)
-        sfor<0, 27>([&](auto T) { v[decltype(T)::value] += weight_of_slot<double>(decltype(T)::value); });
-    scatter<S, CHECK, SOLID>(dst, g.N, n, nb, lm, v);
+        sfor<0, 27>([&](auto T) { v[decltype(T)::value] += lattice_weight<Q, double>(decltype(T)::value); });
+    scatter<S, CHECK, SOLID, Q>(dst, g.N, n, nb, lm, v);
 }
 
 // ------------------------------------------------------------------ adjoint

@@ -76,6 +76,45 @@ __host__ __device__ constexpr R weight_of_slot(int t)
     return R(w1[sa(t)] * w1[sb(t)] * w1[sc(t)]);
 }
 
+// ------------------------------------------------------------------ D3Q19 (Appendix A)
+// The 19 velocities of Eq. (A1) are the first 19 of Eq. (1): every tensor slot
+// except the eight corners, whose three components are all nonzero.  The moment
+// set of Eq. (A2) is {0,1,2}^3 minus the eight triples whose exponents are all
+// >= 1; it contains every triple below each of its members, so the shift N(u)
+// and its inverse restricted to it need no other moment.
+__host__ __device__ constexpr bool corner_population(int t) { return sa(t) != 1 && sb(t) != 1 && sc(t) != 1; }
+__host__ __device__ constexpr bool outside_q19_moments(int t) { return sa(t) >= 1 && sb(t) >= 1 && sc(t) >= 1; }
+
+namespace eqa1 {
+constexpr bool table_ok()
+{
+    for (int t = 0; t < 27; ++t)
+        if ((pop_of_slot(t) < 19) == corner_population(t)) return false;
+    return true;
+}
+static_assert(table_ok(), "the D3Q19 velocities must be the first 19 populations of Eq. (1)");
+}  // namespace eqa1
+
+// Rest-state weight of the velocity in slot t on lattice Q (27 or 19).  D3Q19:
+// 1/3 (rest), 1/18 (faces), 1/36 (edges), 0 for the absent corners.
+template <int Q, typename R>
+__host__ __device__ constexpr R lattice_weight(int t)
+{
+    if constexpr (Q == 27) {
+        return weight_of_slot<R>(t);
+    } else {
+        const int k = (sa(t) != 1) + (sb(t) != 1) + (sc(t) != 1);
+        return R(k == 0 ? 1.0 / 3.0 : (k == 1 ? 1.0 / 18.0 : (k == 2 ? 1.0 / 36.0 : 0.0)));
+    }
+}
+
+// Does lattice Q have a population in slot t?
+template <int Q>
+__host__ __device__ constexpr bool has_slot(int t)
+{
+    return Q == 27 || !corner_population(t);
+}
+
 // e = (1, 0, 1/3): raw moments of w1, i.e. the equilibria of Eq. (15) per unit density.
 __host__ __device__ constexpr double e_of(int k) { return k == 0 ? 1.0 : (k == 1 ? 0.0 : 1.0 / 3.0); }
 
@@ -190,6 +229,32 @@ __device__ __forceinline__ void reconstruct(R (&v)[27], R ux, R uy, R uz)
     axis_pass<0>(v, mk(ux));
     axis_pass<1>(v, mk(uy));
     axis_pass<2>(v, mk(uz));
+}
+
+// D3Q19: post-collision central moments -> populations (Appendix A, Eq. (7)).
+// N^-1 first (its rows for the moments of Eq. (A2) use only those moments); the
+// raw moments outside the set, which vanish for any distribution on the 19
+// velocities, are then set to zero, so that M^-1 of the full tensor set (three
+// passes of M1^-1) returns exactly zero in the eight corner slots.
+template <typename R>
+__device__ __forceinline__ void reconstruct_q19(R (&v)[27], R ux, R uy, R uz)
+{
+    central_unshift(v, ux, uy, uz);
+    sfor<0, 27>([&](auto T) {
+        if constexpr (outside_q19_moments(decltype(T)::value)) v[decltype(T)::value] = R(0);
+    });
+    auto op = [](R &k0, R &k1, R &k2) {
+        const R h2 = R(0.5) * k2;
+        const R fm = fma(R(-0.5), k1, h2);
+        const R fp = fma(R(0.5), k1, h2);
+        const R f0 = k0 - k2;
+        k0 = fm;
+        k1 = f0;
+        k2 = fp;
+    };
+    axis_pass<0>(v, op);
+    axis_pass<1>(v, op);
+    axis_pass<2>(v, op);
 }
 
 // ------------------------------------------------------------------ per-node velocity factors

@@ -59,7 +59,7 @@ def test_desc_layout_matches_header():
 
 def test_strerror_and_version():
     L = _lib()
-    assert L.clbm_abi_version() == 1
+    assert L.clbm_abi_version() == 2
     for code, word in [(0, b"success"), (1, b"invalid"), (2, b"rate"), (3, b"storage"), (4, b"HIP"),
                        (5, b"non-finite")]:
         assert word in L.clbm_strerror(code)
@@ -98,13 +98,15 @@ def test_create_rejects_bad_descriptions_before_any_hip_call(kw, code, word):
     assert rc == code and h.value is None and word in msg
 
 
-def test_create_rejects_bad_storage_and_reserved():
+def test_create_rejects_bad_storage_and_lattice():
     d = _desc()
     d.storage = 7
     assert _create(d)[0] == 3
-    d = _desc()
-    d.reserved = 1
-    assert _create(d)[0] == 1
+    for lat in (2, -1):
+        d = _desc()
+        d.lattice = lat
+        rc, h, msg = _create(d)
+        assert rc == 1 and h.value is None and "lattice" in msg
     assert _create(None)[0] == 1
 
 

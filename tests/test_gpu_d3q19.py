@@ -1,0 +1,163 @@
+"""D3Q19 cascaded LBM (Appendix A) on the HIP path, through the C ABI, against
+the oracle's D3Q19 implementation: initial state, round trips, steps with every
+wall combination, solids, degenerate shapes and all storage types, moments and
+conservation.  Tolerances as for D3Q27 (test_gpu_parity.py)."""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import analytic
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+RATES = np.array([1.0, 1.0, 1.6, 1.2, 1.3, 0.9, 1.1, 1.25, 0.95, 1.05])
+TOL = {"f64": 1e-13, "f32": 5e-8, "f16": 1e-5, "bf16": 8e-5}
+Q19 = "d3q19"
+
+
+def _lattice(dims, walls, storage, rates=RATES, force=(0.0, 0.0, 0.0), field=None, solid=None):
+    from paper_1801_04586_amd import Lattice
+
+    return Lattice(dims, walls, storage, rates, force=force, force_field=field, solid=solid, lattice=Q19)
+
+
+def _start(dims, walls, seed):
+    g = oracle.Geometry(dims, walls)
+    rho0, u0 = workloads.random_state_fields(dims, seed, du=0.05, drho=0.02)
+    f0 = oracle.init(g, rho0, u0, lattice=Q19)
+    f0 = f0 + workloads.random_populations_perturbation(dims, seed + 1, 1e-3)[:19]
+    return g, f0
+
+
+def _compare(dims, walls, storage, steps, seed, with_field=True, solid_frac=0.0, force=(2e-5, -1e-5, 3e-6)):
+    solid = workloads.random_solids(dims, solid_frac, seed + 5) if solid_frac else None
+    g, f0 = _start(dims, walls, seed)
+    field = workloads.gaussian_force(dims, 1e-4, seed + 2) if with_field else None
+    lat = _lattice(dims, walls, storage, force=force, field=field, solid=solid)
+    lat.set_populations(torch.from_numpy(f0))
+    start = lat.populations().cpu().numpy()
+    fl = np.ones(g.shape, bool) if solid is None else solid == 0
+    if storage == "f64":
+        assert np.array_equal(start[:, fl], f0[:, fl])
+    ref = oracle.run(g, start, RATES, steps, force=force, force_field=field, solid=solid, lattice=Q19)
+    lat.step(steps)
+    got = lat.populations().cpu().numpy()
+    assert not lat.uses_fused_pairs
+    lat.close()
+    return np.max(np.abs(got[:, fl] - ref[:, fl]))
+
+
+def test_state_has_19_planes_and_init_is_the_equilibrium():
+    dims, walls = (9, 8, 7), (0, 1, 1)
+    rho0, u0 = workloads.random_state_fields(dims, 3)
+    g = oracle.Geometry(dims, walls)
+    ref = oracle.init(g, rho0, u0, lattice=Q19)
+    for storage, tol in (("f64", 1e-15), ("f32", 1e-9)):
+        lat = _lattice(dims, walls, storage)
+        assert lat.state.shape == (19, 7, 8, 9)
+        lat.init(rho0, u0)
+        got = lat.populations().cpu().numpy()
+        assert np.max(np.abs(got - ref)) < tol, storage
+        lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_set_get_populations_roundtrip(storage):
+    dims, walls = (11, 5, 6), (1, 0, 1)
+    g, f0 = _start(dims, walls, 5)
+    lat = _lattice(dims, walls, storage)
+    lat.set_populations(torch.from_numpy(f0))
+    got = lat.populations().cpu().numpy()
+    tol = {"f64": 0.0, "f32": 1e-9, "f16": 2e-5, "bf16": 2e-4}[storage]
+    assert np.max(np.abs(got - f0)) <= tol
+    ids = [(0, 0, 0), (10, 4, 5), (3, 2, 1)]
+    samp = lat.sample(ids)
+    for k, (x, y, z) in enumerate(ids):
+        assert np.array_equal(samp[:, k], got[:, z, y, x])
+    lat.close()
+
+
+@pytest.mark.parametrize("walls", list(itertools.product((0, 1), repeat=3)))
+def test_step_parity_f64_every_wall_combination(walls):
+    assert _compare((5, 7, 3), walls, "f64", 1, 11) < TOL["f64"]
+    assert _compare((5, 7, 3), walls, "f64", 8, 12, solid_frac=0.15) < TOL["f64"]
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 9), (2, 3, 5), (67, 3, 2), (1, 33, 17)])
+def test_step_parity_f64_degenerate_shapes(dims):
+    assert _compare(dims, (0, 0, 0), "f64", 4, 21) < TOL["f64"]
+    assert _compare(dims, (1, 1, 1), "f64", 4, 22) < TOL["f64"]
+
+
+def test_step_parity_f64_several_blocks_and_ragged_tail():
+    assert _compare((23, 19, 13), (0, 1, 0), "f64", 6, 31, solid_frac=0.1) < TOL["f64"]
+    assert _compare((23, 19, 13), (0, 0, 0), "f64", 6, 32, with_field=False) < TOL["f64"]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("walls,solid_frac", [((0, 0, 0), 0.0), ((0, 1, 1), 0.0), ((1, 0, 1), 0.2)])
+def test_step_parity_reduced_storage_one_step(storage, walls, solid_frac):
+    assert _compare((13, 9, 7), walls, storage, 1, 41, solid_frac=solid_frac) < TOL[storage]
+
+
+def test_step_parity_f32_ten_steps():
+    assert _compare((13, 9, 7), (0, 1, 0), "f32", 10, 43, solid_frac=0.1) < 2e-7
+
+
+def test_moments_and_mass_conservation():
+    dims, walls = (10, 9, 8), (0, 1, 0)
+    solid = workloads.random_solids(dims, 0.1, 51)
+    g, f0 = _start(dims, walls, 52)
+    field = workloads.gaussian_force(dims, 1e-4, 53)
+    lat = _lattice(dims, walls, "f64", force=(1e-5, 0, 0), field=field, solid=solid)
+    lat.set_populations(torch.from_numpy(f0))
+    lat.step(5)
+    f = lat.populations().cpu().numpy()
+    rho, u, tot, nbad = lat.moments()
+    rr, ur = oracle.macro(g, f, force=(1e-5, 0, 0), force_field=field, solid=solid, lattice=Q19)
+    assert nbad == 0
+    assert np.max(np.abs(rho.cpu().numpy() - rr)) < 1e-14
+    assert np.max(np.abs(u.cpu().numpy() - ur)) < 1e-14
+    fl = solid == 0
+    m0 = f0[:, fl].sum()
+    lat.step(20)
+    _, _, tot2, _ = lat.moments(fields=False)
+    assert abs(tot2[0] - m0) < 1e-12 * m0
+    lat.close()
+
+
+def test_adjoint_is_refused_for_d3q19():
+    from paper_1801_04586_amd.clbm import ClbmError
+
+    dims = (6, 5, 4)
+    lat = _lattice(dims, (0, 0, 0), "f32")
+    lat.init()
+    lam = torch.zeros((19,) + lat.shape, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(lam)
+    with pytest.raises(ClbmError) as e:
+        lat.ctx.adjoint_step(lat.state, lam, out)
+    assert e.value.code == 1
+    lat.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-8), ("f32", 1e-4)])
+def test_poiseuille_at_the_nonslip_rule(storage, tol):
+    """Sec. III B on the D3Q19 GPU path: channel 2L = 20, nu = 0.1, F = 5e-6; at the non-slip s3 the
+    profile is the parabola up to the O(F^2) residual the oracle shows (E2 ~ 3e-9)."""
+    H, nu, F = 20, 0.1, 5e-6
+    s3n = workloads.nonslip_s3(workloads.s2_from_nu(nu))
+    lat = _lattice((4, H, 3), (0, 1, 0), storage, rates=workloads.rates(nu, s3=s3n), force=(F, 0, 0))
+    lat.init()
+    lat.step(20000)
+    u = lat.moments()[1].cpu().numpy()
+    lat.close()
+    ua = analytic.poiseuille_steady(H, F, nu)
+    e = analytic.e2(u[0].mean(axis=(0, 2)), ua)
+    print(f"D3Q19 Poiseuille {storage}: E2 = {e:.3e}")
+    assert e < tol
