@@ -85,6 +85,11 @@ def lib():
         L.orc19_step.argtypes = [ip, dp, dp, dp, u8, dp, dp]
         L.orc19_macro.argtypes = [ip, dp, dp, u8, dp, dp, dp]
         L.orc19_init.argtypes = [ip, dp, dp, dp]
+        L.orc_mrt_feq.argtypes = [ctypes.c_double, dp, dp]
+        L.orc_mrt_guo.argtypes = [dp, dp, dp]
+        L.orc_mrt_collide.argtypes = [dp, dp, dp, dp]
+        L.orc_mrt_init.argtypes = [ip, dp, dp, dp]
+        L.orc_step_ex.argtypes = [ip, dp, dp, dp, u8, dp, ctypes.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -312,8 +317,44 @@ def q19_equilibrium(rho, u) -> np.ndarray:
     return out
 
 
+# --------------------------------------------------------------------------- MRT (Appendix B)
+def mrt_feq(rho, u) -> np.ndarray:
+    """Discrete equilibrium f_D^eq of Sec. II B (27 values)."""
+    out = np.zeros(27)
+    lib().orc_mrt_feq(float(rho), _d(_vec3(u)), _d(out))
+    return out
+
+
+def mrt_guo(u, F) -> np.ndarray:
+    """Guo forcing term R_G of Appendix B (27 values)."""
+    out = np.zeros(27)
+    lib().orc_mrt_guo(_d(_vec3(u)), _d(_vec3(F)), _d(out))
+    return out
+
+
+def mrt_collide(f, F, s) -> np.ndarray:
+    """Raw-moment MRT collision of Appendix B at one node: f (27) -> f* (27)."""
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(27)
+    out = np.zeros(27)
+    assert lib().orc_mrt_collide(_d(f), _d(_vec3(F)), _d(_rates(s)), _d(out)) == 0
+    return out
+
+
 # --------------------------------------------------------------------------- lattice
 LATTICES = ("d3q27", "d3q19")
+MODELS = ("cascaded", "mrt")
+
+
+def _wall_u(wall_velocity):
+    """wall_velocity: {(axis, side): (ux, uy, uz)} or a (6, 3) array, face 2*axis + side."""
+    if wall_velocity is None:
+        return None
+    if isinstance(wall_velocity, dict):
+        w = np.zeros((6, 3))
+        for (a, sd), v in wall_velocity.items():
+            w[2 * a + sd] = v
+        return w
+    return np.ascontiguousarray(np.asarray(wall_velocity, dtype=np.float64).reshape(6, 3))
 
 
 def _q(lattice: str) -> int:
@@ -322,32 +363,45 @@ def _q(lattice: str) -> int:
     return 27 if lattice == "d3q27" else 19
 
 
-def init(geom: Geometry, rho0=None, u0=None, lattice: str = "d3q27") -> np.ndarray:
-    """f = f_eq(rho0, u0) at every node; rho0 (nz,ny,nx) or None (=1), u0 (3,nz,ny,nx) or None."""
+def init(geom: Geometry, rho0=None, u0=None, lattice: str = "d3q27", model: str = "cascaded") -> np.ndarray:
+    """f = f_eq(rho0, u0) at every node; rho0 (nz,ny,nx) or None (=1), u0 (3,nz,ny,nx) or None.
+    The cascaded scheme starts from its generalized equilibrium, the MRT from f_D^eq."""
+    assert model in MODELS and (model == "cascaded" or lattice == "d3q27")
     f = np.zeros((_q(lattice),) + geom.shape)
-    fn = lib().orc_init if lattice == "d3q27" else lib().orc19_init
+    if model == "mrt":
+        fn = lib().orc_mrt_init
+    else:
+        fn = lib().orc_init if lattice == "d3q27" else lib().orc19_init
     rc = fn(geom.ptr(), _d(_f64(rho0)), _d(_f64(u0)), _d(f))
     assert rc == 0
     return f
 
 
 def step(geom: Geometry, f, s, force=(0.0, 0.0, 0.0), force_field=None, solid=None,
-         lattice: str = "d3q27") -> np.ndarray:
-    """One time step (Steps 1-4); returns the pre-collision populations at t+1."""
+         lattice: str = "d3q27", model: str = "cascaded", wall_velocity=None) -> np.ndarray:
+    """One time step (Steps 1-4); returns the pre-collision populations at t+1.
+
+    model "mrt": the raw-moment MRT of Appendix B (D3Q27); wall_velocity: moving
+    walls, {(axis, side): (ux, uy, uz)} (D3Q27)."""
     f = _f64(f)
-    assert f.shape[0] == _q(lattice)
+    assert f.shape[0] == _q(lattice) and model in MODELS
     out = np.empty_like(f)
     solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
-    fn = lib().orc_step if lattice == "d3q27" else lib().orc19_step
-    rc = fn(geom.ptr(), _d(_rates(s)), _d(_vec3(force)), _d(_f64(force_field)), _u8(solid), _d(f), _d(out))
+    args = (_d(_rates(s)), _d(_vec3(force)), _d(_f64(force_field)), _u8(solid))
+    if model == "cascaded" and wall_velocity is None:
+        fn = lib().orc_step if lattice == "d3q27" else lib().orc19_step
+        rc = fn(geom.ptr(), *args, _d(f), _d(out))
+    else:
+        assert lattice == "d3q27"
+        rc = lib().orc_step_ex(geom.ptr(), *args, _d(_wall_u(wall_velocity)), MODELS.index(model), _d(f), _d(out))
     assert rc == 0, rc
     return out
 
 
 def run(geom: Geometry, f, s, nsteps, force=(0.0, 0.0, 0.0), force_field=None, solid=None,
-        lattice: str = "d3q27") -> np.ndarray:
+        lattice: str = "d3q27", model: str = "cascaded", wall_velocity=None) -> np.ndarray:
     for _ in range(int(nsteps)):
-        f = step(geom, f, s, force, force_field, solid, lattice)
+        f = step(geom, f, s, force, force_field, solid, lattice, model, wall_velocity)
     return f
 
 

@@ -1019,3 +1019,174 @@ int orc19_init(const int *geom, const double *rho0, const double *u0, double *f)
     }
     return bad ? 2 : 0;
 }
+
+/* ======================================================================== */
+/* Non-orthogonal raw-moment MRT of Appendix B; moving walls                 */
+/* ======================================================================== */
+/*
+ * MRT (Appendix B): the collision of Eq. (5) in raw-moment space, with the
+ * raw moments T = M f of Eq. (14), the equilibria T_eq = M f_D^eq of the
+ * discrete equilibrium f_D^eq = w rho [1 + e.u/c_s^2 + (e.u)^2/(2 c_s^4)
+ * - u^2/(2 c_s^2)] (Sec. II B) and the forcing G = M R_G of Guo et al.,
+ * R_G = w [(e - u)/c_s^2 + (e.u) e/c_s^4] . F:
+ *     T* = T - S (T - T_eq) + (I - S/2) G,   f* = M^-1 T*,
+ * with the same block-diagonal S (Eq. (13)) and u = (sum f e + F/2)/rho.
+ *
+ * Moving walls: a population leaving fluid node x along e_i through wall faces
+ * moving with velocity u_w returns to x reversed with the momentum exchange of
+ * a moving wall, f_opp(i)(x, t+1) = f*_i(x, t) - 2 w_i rho_w (e_i . u_w)/c_s^2,
+ * rho_w = 1.  wall_u[6][3]: velocity of face (axis a, side s) at [2a + s],
+ * side 0 the face below coordinate 0, side 1 the face beyond n_a - 1.  A link
+ * that crosses several faces at once (edges, corners) takes the mean of their
+ * velocities; links into solid nodes see a wall at rest.
+ */
+static double weight27(int i)
+{
+    const int k = abs(EX[i]) + abs(EY[i]) + abs(EZ[i]);
+    return k == 0 ? 8.0 / 27.0 : (k == 1 ? 2.0 / 27.0 : (k == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
+}
+
+/* discrete equilibrium f_D^eq (Sec. II B) */
+void orc_mrt_feq(double rho, const double *u, double *feq)
+{
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; ++i) {
+        const double eu = EX[i] * u[0] + EY[i] * u[1] + EZ[i] * u[2];
+        feq[i] = weight27(i) * rho * (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    }
+}
+
+/* Guo forcing term R_G (Appendix B) */
+void orc_mrt_guo(const double *u, const double *F, double *R)
+{
+    for (int i = 0; i < Q; ++i) {
+        const double e[3] = {(double)EX[i], (double)EY[i], (double)EZ[i]};
+        const double eu = e[0] * u[0] + e[1] * u[1] + e[2] * u[2];
+        double acc = 0.0;
+        for (int a = 0; a < 3; ++a) acc += ((e[a] - u[a]) / CS2 + eu * e[a] / (CS2 * CS2)) * F[a];
+        R[i] = weight27(i) * acc;
+    }
+}
+
+typedef struct {
+    double S[Q * Q];
+    double M[Q * Q];
+    double Minv[Q * Q];
+} orc_mrt_consts;
+
+static int mrt_consts_init(orc_mrt_consts *k, const double *s)
+{
+    orc_matrix_S(s, k->S);
+    orc_matrix_M(k->M);
+    return invert(Q, k->M, k->Minv);
+}
+
+static void mrt_collide_node(const orc_mrt_consts *k, const double *f, const double *F, double *fs)
+{
+    double rho, u[3], feq[Q], R[Q], T[Q], Teq[Q], G[Q], d[Q], Sd[Q], SG[Q], Ts[Q];
+    macro_node(f, F, &rho, u);
+    orc_mrt_feq(rho, u, feq);
+    orc_mrt_guo(u, F, R);
+    matvec(k->M, f, T);
+    matvec(k->M, feq, Teq);
+    matvec(k->M, R, G);
+    for (int a = 0; a < Q; ++a) d[a] = T[a] - Teq[a];
+    matvec(k->S, d, Sd);
+    matvec(k->S, G, SG);
+    for (int a = 0; a < Q; ++a) Ts[a] = T[a] - Sd[a] + G[a] - 0.5 * SG[a];
+    matvec(k->Minv, Ts, fs);
+}
+
+int orc_mrt_collide(const double *f, const double *F, const double *s, double *fs)
+{
+    orc_mrt_consts k;
+    if (mrt_consts_init(&k, s)) return 1;
+    mrt_collide_node(&k, f, F, fs);
+    return 0;
+}
+
+/*
+ * One D3Q27 time step with a choice of collision (model 0: the cascaded scheme
+ * of Sec. II, model 1: the MRT above) and moving walls (wall_u as above, or
+ * NULL for walls at rest).  Other arguments as orc_step.
+ */
+int orc_step_ex(const int *geom, const double *s, const double *Fu, const double *Ff, const uint8_t *solid,
+                const double *wall_u, int model, const double *fin, double *fout)
+{
+    orc_geom G;
+    orc_consts kc;
+    orc_mrt_consts km;
+    if (geom_read(geom, &G)) return 1;
+    if (model != 0 && model != 1) return 3;
+    if (model == 0 ? consts_init(&kc, s) : mrt_consts_init(&km, s)) return 2;
+    const long n = G.n;
+    for (long idx = 0; idx < (long)Q * n; ++idx) fout[idx] = NAN;
+    if (solid)
+        for (long node = 0; node < n; ++node)
+            if (solid[node])
+                for (int i = 0; i < Q; ++i) fout[(long)i * n + node] = fin[(long)i * n + node];
+    int opp[Q];
+    for (int i = 0; i < Q; ++i) opp[i] = opposite(i);
+
+#pragma omp parallel for schedule(static)
+    for (long node = 0; node < n; ++node) {
+        if (solid && solid[node]) continue;
+        const int c[3] = {(int)(node % G.w[0]), (int)((node / G.w[0]) % G.w[1]),
+                          (int)(node / ((long)G.w[0] * G.w[1]))};
+        double f[Q], fs[Q], F[3];
+        for (int i = 0; i < Q; ++i) f[i] = fin[(long)i * n + node];
+        force_at(Fu, Ff, n, node, F);
+        if (model == 0)
+            collide_node(&kc, f, F, fs);
+        else
+            mrt_collide_node(&km, f, F, fs);
+        for (int i = 0; i < Q; ++i) {
+            const int ei[3] = {EX[i], EY[i], EZ[i]};
+            int l[3], partial = 0, beyond = 0;
+            double uw[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < 3; ++a) {
+                const int gc = G.o[a] + c[a] + ei[a];
+                l[a] = locate(&G, a, gc);
+                if (l[a] == -2) partial = 1;
+                if (l[a] == -1) {
+                    const int side = gc < 0 ? 0 : 1;
+                    ++beyond;
+                    if (wall_u)
+                        for (int b = 0; b < 3; ++b) uw[b] += wall_u[3 * (2 * a + side) + b];
+                }
+            }
+            if (partial) continue;
+            long tgt = -1;
+            if (!beyond) {
+                tgt = (long)l[0] + (long)G.w[0] * ((long)l[1] + (long)G.w[1] * l[2]);
+                if (solid && solid[tgt]) tgt = -1;
+            }
+            if (tgt >= 0) {
+                fout[(long)i * n + tgt] = fs[i];
+            } else {
+                double corr = 0.0;
+                if (beyond)
+                    corr = 2.0 * weight27(i) * (ei[0] * uw[0] + ei[1] * uw[1] + ei[2] * uw[2]) / (beyond * CS2);
+                fout[(long)opp[i] * n + node] = fs[i] - corr;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Initial state for the MRT: f = f_D^eq(rho0(x), u0(x)). */
+int orc_mrt_init(const int *geom, const double *rho0, const double *u0, double *f)
+{
+    orc_geom G;
+    if (geom_read(geom, &G)) return 1;
+    const long n = G.n;
+#pragma omp parallel for schedule(static)
+    for (long node = 0; node < n; ++node) {
+        double u[3], fe[Q];
+        const double r = rho0 ? rho0[node] : 1.0;
+        for (int a = 0; a < 3; ++a) u[a] = u0 ? u0[(long)a * n + node] : 0.0;
+        orc_mrt_feq(r, u, fe);
+        for (int i = 0; i < Q; ++i) f[(long)i * n + node] = fe[i];
+    }
+    return 0;
+}
