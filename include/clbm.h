@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 2
+#define CLBM_ABI_VERSION 3
 
 /* Velocity sets: D3Q27 (Eq. (1), moment set Eq. (12)) and D3Q19 (Appendix A,
  * Eq. (A1)-(A6): velocities without the eight corners, moments of Eq. (A2),
@@ -66,6 +66,17 @@ typedef enum clbm_lattice {
     CLBM_D3Q27 = 0,
     CLBM_D3Q19 = 1
 } clbm_lattice;
+
+/* Collision models.  CLBM_CASCADED: the cascaded scheme of Sec. II (Eq. (5),
+ * (13), (15), (16)).  CLBM_MRT: the non-orthogonal raw-moment MRT of
+ * Appendix B on D3Q27 -- raw moments T = M f of Eq. (14), equilibria
+ * M f_D^eq of the discrete equilibrium of Sec. II B, forcing M R_G of Guo et
+ * al., T* = T - S (T - T_eq) + (I - S/2) G with the same S (Eq. (13)); its
+ * initial state (clbm_init) is f_D^eq.  The MRT has no adjoint. */
+typedef enum clbm_collision {
+    CLBM_CASCADED = 0,
+    CLBM_MRT = 1
+} clbm_collision;
 
 typedef enum clbm_dtype {
     CLBM_F64 = 0,
@@ -103,6 +114,18 @@ typedef struct clbm_desc {
     /* Solid mask: device uint8 [N], nonzero = solid, or NULL (all fluid).  Read
      * once, by clbm_create, which derives the context's link table from it. */
     const uint8_t *solid;
+    int32_t collision;        /* clbm_collision; CLBM_MRT needs CLBM_D3Q27 */
+    int32_t reserved;         /* must be 0 */
+    /* Velocities of the wall faces (host copy taken by clbm_create):
+     * wall_velocity[2a + s] for axis a, side s = 0 the face below coordinate 0,
+     * s = 1 the face beyond n_a - 1.  A population that leaves a fluid node
+     * along e_i through moving faces returns reversed with the momentum
+     * exchange -2 w_i (e_i . u_w)/c_s^2 (wall density 1), u_w the mean velocity
+     * of the faces the link crosses; links into solid nodes see a wall at
+     * rest.  Faces of periodic axes must have zero velocity.  All zero: the
+     * walls of Sec. III, at rest (used for the lid-driven cavity of
+     * Appendix B). */
+    double wall_velocity[6][3];
 } clbm_desc;
 
 typedef struct clbm_ctx clbm_ctx;
@@ -198,7 +221,8 @@ int clbm_set_populations(clbm_ctx *ctx, const double *f, void *state);
  * Eq. (1) order, distinct buffers; zero on solid nodes.
  * dJdF: device [3][N] of the adjoint type or NULL; dJ/dF(x) of this step is
  * added to it.  dJds: device FP64 [10] or NULL; dJ/ds_k of this step (summed
- * over nodes in FP64, fixed order) is added to it. */
+ * over nodes in FP64, fixed order) is added to it.  D3Q27 cascaded scheme
+ * only (moving walls allowed: their momentum exchange is a constant). */
 int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, void *dJdF,
                       double *dJds);
 

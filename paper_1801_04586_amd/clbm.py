@@ -23,10 +23,12 @@ STORAGE_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float1
 # arithmetic / adjoint / force-field type per storage
 REAL_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float32, "bf16": torch.float32}
 RATE_NAMES = ("s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6")
-ABI_VERSION = 2  # CLBM_ABI_VERSION of include/clbm.h
+ABI_VERSION = 3  # CLBM_ABI_VERSION of include/clbm.h
 CLBM_D3Q27, CLBM_D3Q19 = 0, 1
 LATTICE = {"d3q27": CLBM_D3Q27, "d3q19": CLBM_D3Q19}
 LATTICE_Q = {"d3q27": 27, "d3q19": 19}
+CLBM_CASCADED, CLBM_MRT = 0, 1
+COLLISION = {"cascaded": CLBM_CASCADED, "mrt": CLBM_MRT}
 
 
 class ClbmError(RuntimeError):
@@ -48,6 +50,9 @@ class Desc(ctypes.Structure):
         ("force_scale", ctypes.c_double),
         ("force", ctypes.c_void_p),
         ("solid", ctypes.c_void_p),
+        ("collision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("wall_velocity", ctypes.c_double * 18),
     ]
 
 
@@ -199,9 +204,26 @@ class Context:
         self._call("clbm_loss_seed", _ptr(state), _ptr(u_target), _ptr(lam_out), _ptr(dJdF), _ptr(J))
 
 
+def wall_velocity_array(wall_velocity) -> np.ndarray:
+    """Face velocities as a (6, 3) array, face 2 * axis + side (side 1 beyond n - 1); accepts
+    None, a {(axis, side): (ux, uy, uz)} dict or anything shaped (6, 3)."""
+    w = np.zeros((6, 3))
+    if wall_velocity is None:
+        return w
+    if isinstance(wall_velocity, dict):
+        for (a, sd), v in wall_velocity.items():
+            w[2 * int(a) + int(sd)] = v
+        return w
+    return np.asarray(wall_velocity, dtype=np.float64).reshape(6, 3).copy()
+
+
 def make_desc(dims, walls=(0, 0, 0), storage="f32", rates=None, force=(0.0, 0.0, 0.0), force_field=None,
-              force_scale=1.0, solid=None, lattice="d3q27") -> Desc:
+              force_scale=1.0, solid=None, lattice="d3q27", collision="cascaded", wall_velocity=None) -> Desc:
     d = Desc()
+    d.collision = COLLISION[collision]
+    d.reserved = 0
+    for k, v in enumerate(wall_velocity_array(wall_velocity).reshape(18)):
+        d.wall_velocity[k] = float(v)
     d.nx, d.ny, d.nz = (int(v) for v in dims)
     for a in range(3):
         d.wall[a] = int(walls[a])
@@ -235,11 +257,14 @@ class Lattice:
     storage in {"f64", "f32", "f16", "bf16"}; rates = the 10 rates of Eq. (13);
     force = uniform force density; force_field = (3, nz, ny, nx) field added to
     it (times force_scale); solid = (nz, ny, nx) mask, nonzero = solid;
-    lattice = "d3q27" (Eq. (1)) or "d3q19" (Appendix A).
+    lattice = "d3q27" (Eq. (1)) or "d3q19" (Appendix A); collision = "cascaded"
+    (Sec. II) or "mrt" (the raw-moment MRT of Appendix B, D3Q27); wall_velocity =
+    moving wall faces, {(axis, side): (ux, uy, uz)} (side 1 beyond n - 1).
     """
 
     def __init__(self, dims: Sequence[int], walls=(0, 0, 0), storage="f32", rates=None, force=(0.0, 0.0, 0.0),
-                 force_field=None, force_scale=1.0, solid=None, device=None, lattice="d3q27"):
+                 force_field=None, force_scale=1.0, solid=None, device=None, lattice="d3q27", collision="cascaded",
+                 wall_velocity=None):
         if not torch.cuda.is_available():
             raise RuntimeError("clbm needs a GPU (HIP); none is visible")
         self.device = torch.device(device if device is not None else "cuda")
@@ -250,6 +275,8 @@ class Lattice:
         self.walls = tuple(int(w) for w in walls)
         self.storage = storage
         self.lattice = lattice
+        self.collision = collision
+        self.wall_velocity = wall_velocity_array(wall_velocity)
         self.q = LATTICE_Q[lattice]
         self.real = REAL_TORCH[storage]
         self.force_field = _dev_tensor(force_field, self.real, self.device, (3,) + self.shape)
@@ -258,7 +285,7 @@ class Lattice:
         self.force = tuple(float(v) for v in force)
         self.force_scale = float(force_scale)
         desc = make_desc(self.dims, self.walls, storage, self.rates, self.force, self.force_field, force_scale,
-                         self.solid, lattice)
+                         self.solid, lattice, collision, self.wall_velocity)
         self.ctx = Context(desc, self.device)
         self.bufs = [torch.empty((self.q,) + self.shape, dtype=STORAGE_TORCH[storage], device=self.device)
                      for _ in range(2)]

@@ -76,6 +76,18 @@ int validate_desc(const clbm_desc *d)
         if (d->wall[a] != 0 && d->wall[a] != 1) return fail(nullptr, CLBM_EINVAL, "wall flags must be 0 or 1");
     if (d->storage < CLBM_F64 || d->storage > CLBM_BF16) return fail(nullptr, CLBM_EDTYPE, "unknown storage type");
     if (d->lattice != CLBM_D3Q27 && d->lattice != CLBM_D3Q19) return fail(nullptr, CLBM_EINVAL, "unknown lattice");
+    if (d->collision != CLBM_CASCADED && d->collision != CLBM_MRT)
+        return fail(nullptr, CLBM_EINVAL, "unknown collision model");
+    if (d->collision == CLBM_MRT && d->lattice != CLBM_D3Q27)
+        return fail(nullptr, CLBM_EINVAL, "the MRT collision needs the D3Q27 lattice");
+    if (d->reserved != 0) return fail(nullptr, CLBM_EINVAL, "reserved field must be 0");
+    for (int f = 0; f < 6; ++f)
+        for (int b = 0; b < 3; ++b) {
+            const double w = d->wall_velocity[f][b];
+            if (!std::isfinite(w)) return fail(nullptr, CLBM_EINVAL, "wall velocity not finite");
+            if (w != 0.0 && !d->wall[f / 2])
+                return fail(nullptr, CLBM_EINVAL, "a face of a periodic axis cannot move");
+        }
     int rc = validate_rates(nullptr, d->s);
     if (rc) return rc;
     for (int a = 0; a < 3; ++a)
@@ -147,11 +159,12 @@ int dispatch(const clbm_ctx *c, F &&f)
     return c->d.lattice == CLBM_D3Q19 ? dispatch_storage<19>(c, f) : dispatch_storage<27>(c, f);
 }
 
-// The adjoint and the loss exist for D3Q27 only.
+// The adjoint and the loss exist for the D3Q27 cascaded scheme only.
 template <typename F>
 int dispatch_d3q27(clbm_ctx *c, F &&f)
 {
     if (c->d.lattice != CLBM_D3Q27) return fail(c, CLBM_EINVAL, "the adjoint needs the D3Q27 lattice");
+    if (c->d.collision != CLBM_CASCADED) return fail(c, CLBM_EINVAL, "the adjoint needs the cascaded collision");
     return dispatch_storage<27>(c, f);
 }
 
@@ -171,26 +184,34 @@ bool high_rates_one(const clbm_ctx *c)
     return true;
 }
 
+// Collision variant of the step kernels for a context.
+int collision_of(const clbm_ctx *c)
+{
+    if (c->d.collision == CLBM_MRT) return kMrt;
+    return c->d.lattice == CLBM_D3Q27 && high_rates_one(c) ? kCascadedHigh1 : kCascaded;
+}
+
 int launch_step(clbm_ctx *c, const void *src, void *dst)
 {
-    const bool high1 = high_rates_one(c);
+    const int coll = collision_of(c);
     return dispatch(c, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
         using R = typename Vt::R;
-        auto go = [&](auto h) {
-            constexpr bool H = decltype(h)::value;
-            hipLaunchKernelGGL((k_step<S, Vt::check, Vt::solid, Vt::field, H, Vt::q>), dim3(node_blocks(c)),
+        auto go = [&](auto cc) {
+            constexpr int C = decltype(cc)::value;
+            hipLaunchKernelGGL((k_step<S, Vt::check, Vt::solid, Vt::field, C, Vt::q>), dim3(node_blocks(c)),
                                dim3(kBlock), 0, c->stream, static_cast<const S *>(src), static_cast<S *>(dst), c->geom,
                                c->links, static_cast<const R *>(c->d.force), make_forcing<R>(c->d),
                                make_rates<R>(c->d.s));
             return check_launch(c, "step kernel launch");
         };
-        // D3Q19 always takes the general collision
-        if constexpr (Vt::q == 27)
-            return high1 ? go(std::true_type{}) : go(std::false_type{});
-        else
-            return go(std::false_type{});
+        // D3Q19 takes the general cascaded collision only
+        if constexpr (Vt::q == 27) {
+            if (coll == kMrt) return go(std::integral_constant<int, kMrt>{});
+            if (coll == kCascadedHigh1) return go(std::integral_constant<int, kCascadedHigh1>{});
+        }
+        return go(std::integral_constant<int, kCascaded>{});
     });
 }
 
@@ -218,19 +239,21 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
     tg.zchunk = (c->geom.nz + nchunks - 1) / nchunks;
     nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
     const unsigned blocks = tiles * nchunks;
-    const bool high1 = high_rates_one(c);
+    const int coll = collision_of(c);
     auto go = [&](auto tag, auto field_tag) {
         using S = decltype(tag);
         using R = typename Traits<S>::R;
         constexpr bool FIELD = decltype(field_tag)::value;
-        auto launch = [&](auto h) {
-            constexpr bool H = decltype(h)::value;
-            hipLaunchKernelGGL((k_step2<S, FIELD, H>), dim3(blocks), dim3(kT2Block), 0, c->stream,
+        auto launch = [&](auto cc) {
+            constexpr int C = decltype(cc)::value;
+            hipLaunchKernelGGL((k_step2<S, FIELD, C>), dim3(blocks), dim3(kT2Block), 0, c->stream,
                                static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg,
                                static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
             return check_launch(c, "fused two-step kernel launch");
         };
-        return high1 ? launch(std::true_type{}) : launch(std::false_type{});
+        if (coll == kMrt) return launch(std::integral_constant<int, kMrt>{});
+        if (coll == kCascadedHigh1) return launch(std::integral_constant<int, kCascadedHigh1>{});
+        return launch(std::integral_constant<int, kCascaded>{});
     };
     return c->d.force != nullptr ? go(float{}, std::true_type{}) : go(float{}, std::false_type{});
 }
@@ -276,6 +299,12 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
     g.dnx.init(g.nx);
     g.dny.init(g.ny);
     for (int a = 0; a < 3; ++a) g.wall[a] = desc->wall[a];
+    g.moving = 0;
+    for (int f = 0; f < 6; ++f)
+        for (int b = 0; b < 3; ++b) {
+            g.wu[f][b] = desc->wall_velocity[f][b];
+            if (desc->wall_velocity[f][b] != 0.0) g.moving = 1;
+        }
     std::snprintf(c->err, sizeof(c->err), "no error");
     hipError_t e = hipMalloc(&c->partials, sizeof(double) * kMaxBlocks * kPartialStride);
     if (e != hipSuccess) {
@@ -370,8 +399,15 @@ int clbm_init(clbm_ctx *ctx, void *state, const double *rho0, const double *u0)
     return dispatch(ctx, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
-        hipLaunchKernelGGL((k_init<S, Vt::check, Vt::solid, Vt::q>), dim3(node_blocks(ctx)), dim3(kBlock), 0, ctx->stream,
-                           static_cast<S *>(state), ctx->geom, ctx->links, rho0, u0);
+        if constexpr (Vt::q == 27) {
+            if (ctx->d.collision == CLBM_MRT) {
+                hipLaunchKernelGGL((k_init<S, Vt::check, Vt::solid, 27, true>), dim3(node_blocks(ctx)), dim3(kBlock),
+                                   0, ctx->stream, static_cast<S *>(state), ctx->geom, ctx->links, rho0, u0);
+                return check_launch(ctx, "init kernel launch");
+            }
+        }
+        hipLaunchKernelGGL((k_init<S, Vt::check, Vt::solid, Vt::q, false>), dim3(node_blocks(ctx)), dim3(kBlock), 0,
+                           ctx->stream, static_cast<S *>(state), ctx->geom, ctx->links, rho0, u0);
         return check_launch(ctx, "init kernel launch");
     });
 }

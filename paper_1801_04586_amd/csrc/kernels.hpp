@@ -84,6 +84,8 @@ struct Geom {
     uint32_t N, nx, ny, nz, nxy;
     FastDiv dnx, dny;
     int32_t wall[3];
+    int32_t moving;    // some wall face moves
+    double wu[6][3];   // velocity of wall face (axis a, side s) at [2a + s]; side 1 lies beyond n_a - 1
 };
 
 // Pull sources of one node.  Index a = e + 1 per axis: xs[a] is the x of the node
@@ -164,8 +166,35 @@ __device__ __forceinline__ void store_at(T *__restrict__ base, uint32_t byte_off
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
+// Momentum exchange of moving walls for a blocked pull of slot T: the
+// population that left along -e through the wall faces it crossed returns as
+// slot T with + 2 w (e . u_w)/c_s^2, u_w the mean velocity of those faces (zero
+// when the link is blocked by a solid node only).
+template <int T, int Q, typename R>
+__device__ __forceinline__ R wall_term(const Nbr &nb, const Geom &g)
+{
+    R ux = R(0), uy = R(0), uz = R(0);
+    int cnt = 0;
+    auto add = [&](int face) {
+        ux += static_cast<R>(g.wu[face][0]);
+        uy += static_cast<R>(g.wu[face][1]);
+        uz += static_cast<R>(g.wu[face][2]);
+        ++cnt;
+    };
+    // pulling slot index 0 (e = -1) reads x + 1: crosses the face beyond n - 1; index 2 the face below 0
+    if constexpr (sa(T) != 1)
+        if (!nb.vx[sa(T)]) add(0 + (sa(T) == 0 ? 1 : 0));
+    if constexpr (sb(T) != 1)
+        if (!nb.vy[sb(T)]) add(2 + (sb(T) == 0 ? 1 : 0));
+    if constexpr (sc(T) != 1)
+        if (!nb.vz[sc(T)]) add(4 + (sc(T) == 0 ? 1 : 0));
+    if (cnt == 0) return R(0);
+    const R eu = R(sa(T) - 1) * ux + R(sb(T) - 1) * uy + R(sc(T) - 1) * uz;
+    return R(6) * lattice_weight<Q, R>(T) * eu / R(cnt);
+}
+
 template <typename S, bool CHECK, bool SOLID, bool REV, int Q, typename R>
-__device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
+__device__ __forceinline__ void gather_links(const S *__restrict__ buf, const Geom &g, uint32_t n, const Nbr &nb,
                                              uint32_t lm, R (&v)[27]);
 
 // Gather of Eq. (8): v[t] = population of slot t arriving at node n, as a real
@@ -184,8 +213,8 @@ __host__ __device__ constexpr uint32_t all_links()
 }
 
 template <typename S, bool CHECK, bool SOLID, bool REV, int Q = 27, typename R>
-__device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb, uint32_t lm,
-                                       R (&v)[27])
+__device__ __forceinline__ void gather(const S *__restrict__ buf, const Geom &g, uint32_t n, const Nbr &nb,
+                                       uint32_t lm, R (&v)[27])
 {
     if constexpr (CHECK) {
         bool open;
@@ -194,18 +223,19 @@ __device__ __forceinline__ void gather(const S *__restrict__ buf, uint32_t N, ui
         else
             open = nb.vx[0] && nb.vx[2] && nb.vy[0] && nb.vy[2] && nb.vz[0] && nb.vz[2];
         if (__all(open))
-            gather_links<S, false, false, REV, Q>(buf, N, n, nb, lm, v);
+            gather_links<S, false, false, REV, Q>(buf, g, n, nb, lm, v);
         else
-            gather_links<S, true, SOLID, REV, Q>(buf, N, n, nb, lm, v);
+            gather_links<S, true, SOLID, REV, Q>(buf, g, n, nb, lm, v);
     } else {
-        gather_links<S, false, false, REV, Q>(buf, N, n, nb, lm, v);
+        gather_links<S, false, false, REV, Q>(buf, g, n, nb, lm, v);
     }
 }
 
 template <typename S, bool CHECK, bool SOLID, bool REV, int Q, typename R>
-__device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb,
+__device__ __forceinline__ void gather_links(const S *__restrict__ buf, const Geom &g, uint32_t n, const Nbr &nb,
                                              uint32_t lm, R (&v)[27])
 {
+    const uint32_t N = g.N;
     constexpr uint32_t es = sizeof(S);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
@@ -226,6 +256,8 @@ __device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t
                 else
                     val = load_at(buf + static_cast<size_t>(ib) * N, n * es);
                 v[t] = static_cast<R>(to_real(val));
+                if constexpr (!REV)
+                    if (g.moving && !ok) v[t] += wall_term<t, Q, R>(nb, g);
             } else {
                 v[t] = static_cast<R>(to_real(load_at(Pi, off * es)));
             }
@@ -235,14 +267,15 @@ __device__ __forceinline__ void gather_links(const S *__restrict__ buf, uint32_t
 
 // Inverse of gather: write the value of slot t of node n where gather() reads it.
 template <typename S, bool CHECK, bool SOLID, int Q, typename R>
-__device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_t n, const Nbr &nb, uint32_t lm,
+__device__ __forceinline__ void scatter(S *__restrict__ buf, const Geom &g, uint32_t n, const Nbr &nb, uint32_t lm,
                                         const R (&v)[27])
 {
+    const uint32_t N = g.N;
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         constexpr int i = pop_of_slot(t);
         S *__restrict__ Pi = buf + static_cast<size_t>(i) * N;
-        const S val = to_store<S>(v[t]);
+        S val = to_store<S>(v[t]);
         if constexpr (!has_slot<Q>(t)) {
             // no population in this slot
         } else if constexpr (t == 13) {
@@ -252,6 +285,7 @@ __device__ __forceinline__ void scatter(S *__restrict__ buf, uint32_t N, uint32_
             const bool ok = link_open<t, false, SOLID>(nb, lm, off);
             if constexpr (CHECK) {
                 constexpr int ib = pop_of_slot(26 - t);
+                if (g.moving && !ok) val = to_store<S>(v[t] - wall_term<t, Q, R>(nb, g));
                 S *p = ok ? (Pi + off) : (buf + static_cast<size_t>(ib) * N + n);
                 *p = val;
             } else {
@@ -335,14 +369,26 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
 }
 
 // ------------------------------------------------------------------ forward step
+// Collision models of the step kernels.
+enum Collision : int {
+    kCascaded = 0,       // Sec. II B, Eq. (5)
+    kCascadedHigh1 = 1,  // the same when every rate above second order is one (collide_high1)
+    kMrt = 2,            // raw-moment MRT with Guo forcing (Appendix B)
+};
+
 // Steps 1-3 of Sec. II B on one node's deviations d = f - w (in place, registers).
-// HIGH1: every rate above second order is one (collide_high1).  Q = 19: the D3Q19
-// scheme of Appendix A on the same slots (corner slots hold 0 on entry and exit).
-template <bool HIGH1 = false, int Q = 27, typename R>
+// Q = 19: the D3Q19 scheme of Appendix A on the same slots (corner slots hold 0
+// on entry and exit).
+template <int COLL = kCascaded, int Q = 27, typename R>
 __device__ __forceinline__ void node_update(R (&v)[27], R Fx, R Fy, R Fz, const Rates<R> &rt)
 {
+    if constexpr (COLL == kMrt) {
+        static_assert(Q == 27, "the MRT runs on D3Q27");
+        collide_mrt(v, Fx, Fy, Fz, rt);
+        return;
+    }
     if constexpr (Q == 19) {
-        static_assert(!HIGH1, "D3Q19 uses the general collision");
+        static_assert(COLL == kCascaded, "D3Q19 uses the general collision");
         raw_moments(v);
         const R drho = v[slot(0, 0, 0)];
         const R inv_rho = R(1) / (R(1) + drho);
@@ -355,7 +401,7 @@ __device__ __forceinline__ void node_update(R (&v)[27], R Fx, R Fy, R Fz, const 
         reconstruct_q19(v, ux, uy, uz);
         return;
     }
-    if constexpr (HIGH1) {
+    if constexpr (COLL == kCascadedHigh1) {
         R ux, uy, uz;
         collide_high1(v, Fx, Fy, Fz, rt, ux, uy, uz);
         reconstruct(v, ux, uy, uz);
@@ -378,7 +424,7 @@ __device__ __forceinline__ void node_update(R (&v)[27], R Fx, R Fy, R Fz, const 
 // stores its (never read) entries, so that every wavefront writes whole cache
 // lines: lanes that skipped their stores would leave partially written lines,
 // which cost far more memory time than the extra bytes.
-template <typename S, bool CHECK, bool SOLID, bool FIELD, bool HIGH1, int Q>
+template <typename S, bool CHECK, bool SOLID, bool FIELD, int COLL, int Q>
 __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src, S *__restrict__ dst, const Geom &g,
                                           const uint32_t *__restrict__ links,
                                           const typename Traits<S>::R *__restrict__ field,
@@ -393,7 +439,7 @@ __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src,
     neighbours(g, n, nb);
     R v[27];
     if (!SOLID || lm != 0u) {
-        gather<S, CHECK, SOLID, false, Q>(src, g.N, n, nb, lm, v);
+        gather<S, CHECK, SOLID, false, Q>(src, g, n, nb, lm, v);
         if constexpr (!Traits<S>::kDev)
             sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= lattice_weight<Q, R>(decltype(T)::value); });
     } else {
@@ -402,7 +448,7 @@ __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src,
 
     R Fx, Fy, Fz;
     force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
-    node_update<HIGH1, Q>(v, Fx, Fy, Fz, rt);
+    node_update<COLL, Q>(v, Fx, Fy, Fz, rt);
 
     const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
     sfor<0, 27>([&](auto TT) {
@@ -415,13 +461,13 @@ __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src,
     });
 }
 
-template <typename S, bool CHECK, bool SOLID, bool FIELD, bool HIGH1, int Q>
+template <typename S, bool CHECK, bool SOLID, bool FIELD, int COLL, int Q>
 __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *__restrict__ dst, Geom g,
                                                  const uint32_t *__restrict__ links,
                                                  const typename Traits<S>::R *__restrict__ field,
                                                  Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
 {
-    step_node<S, CHECK, SOLID, FIELD, HIGH1, Q>(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x, src, dst, g, links,
+    step_node<S, CHECK, SOLID, FIELD, COLL, Q>(xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x, src, dst, g, links,
                                       field, fo, rt);
 }
 
@@ -457,7 +503,7 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
     return static_cast<uint32_t>(r < 0 ? r + static_cast<int>(n) : r);
 }
 
-template <typename S, bool FIELD, bool HIGH1>
+template <typename S, bool FIELD, int COLL>
 __global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg,
                                                     const typename Traits<S>::R *__restrict__ field,
                                                     Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
@@ -516,7 +562,7 @@ __global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S
         sfor<0, 27>([&](auto T) { v[decltype(T)::value] = to_real(pre[decltype(T)::value]); });
         R Fx, Fy, Fz;
         force_from<FIELD>(fo, pFx, pFy, pFz, Fx, Fy, Fz);
-        node_update<HIGH1>(v, Fx, Fy, Fz, rt);
+        node_update<COLL>(v, Fx, Fy, Fz, rt);
         const int sA = ring_slot(0, p), sB = ring_slot(1, p), sC = ring_slot(2, p);
         sfor<0, 27>([&](auto TT) {
             constexpr int t = decltype(TT)::value;
@@ -541,7 +587,7 @@ __global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S
         });
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
-        node_update<HIGH1>(v, Fx, Fy, Fz, rt);
+        node_update<COLL>(v, Fx, Fy, Fz, rt);
         const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
         sfor<0, 27>([&](auto TT) {
             constexpr int t = decltype(TT)::value;
@@ -621,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const S *__restrict__ src, G
         Nbr nb;
         neighbours(g, n, nb);
         double v[27];
-        gather<S, CHECK, SOLID, false, Q>(src, g.N, n, nb, lm, v);
+        gather<S, CHECK, SOLID, false, Q>(src, g, n, nb, lm, v);
         if constexpr (!Traits<S>::kDev)
             sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= lattice_weight<Q, double>(decltype(T)::value); });
         raw_moments(v);
@@ -664,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_get_populations(const S *__restrict_
     Nbr nb;
     neighbours(g, n, nb);
     double v[27];
-    gather<S, CHECK, SOLID, false, Q>(src, g.N, n, nb, lm, v);
+    gather<S, CHECK, SOLID, false, Q>(src, g, n, nb, lm, v);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         if constexpr (has_slot<Q>(t)) {
@@ -695,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_populations(const S *__restri
     Nbr nb;
     neighbours(g, n, nb);
     double v[27];
-    gather<S, CHECK, SOLID, false, Q>(src, g.N, n, nb, lm, v);
+    gather<S, CHECK, SOLID, false, Q>(src, g, n, nb, lm, v);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         if constexpr (has_slot<Q>(t)) {
@@ -727,12 +773,13 @@ __global__ __launch_bounds__(kBlock) void k_set_populations(const double *__rest
             v[t] = 0.0;
         }
     });
-    scatter<S, CHECK, SOLID, Q>(dst, g.N, n, nb, lm, v);
+    scatter<S, CHECK, SOLID, Q>(dst, g, n, nb, lm, v);
 }
 
 // f = f_eq(rho0, u0): the generalized equilibrium (NM)^-1 T_eq, computed in FP64
-// as the reconstruction of T_eq - N(u) M w.
-template <typename S, bool CHECK, bool SOLID, int Q>
+// as the reconstruction of T_eq - N(u) M w; DISCRETE (the MRT of Appendix B):
+// the discrete equilibrium f_D^eq of Sec. II B.
+template <typename S, bool CHECK, bool SOLID, int Q, bool DISCRETE>
 __global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, const uint32_t *__restrict__ links,
                                                  const double *__restrict__ rho0, const double *__restrict__ u0)
 {
@@ -748,14 +795,19 @@ __global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, co
     const double uz = u0 ? u0[2 * static_cast<size_t>(g.N) + n] : 0.0;
     const AxisU<double> X(ux), Y(uy), Z(uz);
     double v[27];
-    equilibrium_moments(v, drho, X, Y, Z);
-    if constexpr (Q == 19)
-        reconstruct_q19(v, ux, uy, uz);
-    else
-        reconstruct(v, ux, uy, uz);
+    if constexpr (DISCRETE) {
+        static_assert(Q == 27, "the discrete equilibrium is the D3Q27 one");
+        discrete_equilibrium_dev(v, drho, ux, uy, uz);
+    } else {
+        equilibrium_moments(v, drho, X, Y, Z);
+        if constexpr (Q == 19)
+            reconstruct_q19(v, ux, uy, uz);
+        else
+            reconstruct(v, ux, uy, uz);
+    }
     if constexpr (!Traits<S>::kDev)
         sfor<0, 27>([&](auto T) { v[decltype(T)::value] += lattice_weight<Q, double>(decltype(T)::value); });
-    scatter<S, CHECK, SOLID, Q>(dst, g.N, n, nb, lm, v);
+    scatter<S, CHECK, SOLID, Q>(dst, g, n, nb, lm, v);
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -806,7 +858,7 @@ __device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const
         // ---- forward recomputation: T~ (full central moments) at this node
         R tt[27];
         if (fluid) {
-            gather<S, CHECK, SOLID, false>(state, g.N, n, nb, lm, tt);
+            gather<S, CHECK, SOLID, false>(state, g, n, nb, lm, tt);
             if constexpr (!Traits<S>::kDev)
                 sfor<0, 27>([&](auto T) { tt[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
         } else {
@@ -836,7 +888,7 @@ __device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const
         // ---- adjoint of f*: gather lambda(t+1) along +e, then through M^-1 and N(-u)
         R a[27];
         if (fluid)
-            gather<R, CHECK, SOLID, true>(lam_next, g.N, n, nb, lm, a);
+            gather<R, CHECK, SOLID, true>(lam_next, g, n, nb, lm, a);
         else
             sfor<0, 27>([&](auto T) { a[decltype(T)::value] = R(0); });
         reconstruct_raw_T(a);
@@ -985,7 +1037,7 @@ __global__ __launch_bounds__(kBlock) void k_loss(const S *__restrict__ state, Ge
         neighbours(g, n, nb);
         R v[27];
         if (fluid) {
-            gather<S, CHECK, SOLID, false>(state, g.N, n, nb, lm, v);
+            gather<S, CHECK, SOLID, false>(state, g, n, nb, lm, v);
             if constexpr (!Traits<S>::kDev)
                 sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= weight_of_slot<R>(decltype(T)::value); });
         } else {

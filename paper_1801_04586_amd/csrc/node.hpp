@@ -236,13 +236,11 @@ __device__ __forceinline__ void reconstruct(R (&v)[27], R ux, R uy, R uz)
 // raw moments outside the set, which vanish for any distribution on the 19
 // velocities, are then set to zero, so that M^-1 of the full tensor set (three
 // passes of M1^-1) returns exactly zero in the eight corner slots.
+// M^-1 as three passes of M1^-1: raw (k0, k1, k2) -> (f(-1), f(0), f(+1)) =
+// ((k2 - k1)/2, k0 - k2, (k2 + k1)/2) along each axis.
 template <typename R>
-__device__ __forceinline__ void reconstruct_q19(R (&v)[27], R ux, R uy, R uz)
+__device__ __forceinline__ void inverse_raw_moments(R (&v)[27])
 {
-    central_unshift(v, ux, uy, uz);
-    sfor<0, 27>([&](auto T) {
-        if constexpr (outside_q19_moments(decltype(T)::value)) v[decltype(T)::value] = R(0);
-    });
     auto op = [](R &k0, R &k1, R &k2) {
         const R h2 = R(0.5) * k2;
         const R fm = fma(R(-0.5), k1, h2);
@@ -255,6 +253,16 @@ __device__ __forceinline__ void reconstruct_q19(R (&v)[27], R ux, R uy, R uz)
     axis_pass<0>(v, op);
     axis_pass<1>(v, op);
     axis_pass<2>(v, op);
+}
+
+template <typename R>
+__device__ __forceinline__ void reconstruct_q19(R (&v)[27], R ux, R uy, R uz)
+{
+    central_unshift(v, ux, uy, uz);
+    sfor<0, 27>([&](auto T) {
+        if constexpr (outside_q19_moments(decltype(T)::value)) v[decltype(T)::value] = R(0);
+    });
+    inverse_raw_moments(v);
 }
 
 // ------------------------------------------------------------------ per-node velocity factors
@@ -430,6 +438,120 @@ __device__ __forceinline__ void collide_high1(R (&v)[27], R Fx, R Fy, R Fz, cons
     v[slot(2, 0, 0)] = c200 - fma(s.s[R_S2], nx, tr);
     v[slot(0, 2, 0)] = c020 - fma(s.s[R_S2], ny, tr);
     v[slot(0, 0, 2)] = c002 - fma(s.s[R_S2], nz, tr);
+}
+
+// ------------------------------------------------------------------ raw-moment MRT (Appendix B)
+// Sum over the D3Q27 weights of e^k along one axis: 1, 0, 1/3, 0, 1/3 for k = 0..4.
+__host__ __device__ constexpr double axis_moment(int k) { return k == 0 ? 1.0 : (k % 2 ? 0.0 : 1.0 / 3.0); }
+__host__ __device__ constexpr double weight_moment(int m, int n, int p)
+{
+    return axis_moment(m) * axis_moment(n) * axis_moment(p);
+}
+__host__ __device__ constexpr int bump(int k, int axis, int a) { return k + (axis == a ? 1 : 0); }
+
+// Raw moment (m, n, p) of sum_i w_i e_i^(mnp) (e_i . u)^ and (e_i . u)(e_i . V):
+// first[a] = W(e + 1_a), second[a][b] = W(e + 1_a + 1_b), with W the weight moment.
+template <int M, int N, int P, typename R>
+__device__ __forceinline__ R weighted_dot1(const R (&u)[3])
+{
+    R acc = R(0);
+    sfor<0, 3>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        constexpr double c = weight_moment(bump(M, 0, a), bump(N, 1, a), bump(P, 2, a));
+        if constexpr (c != 0.0) acc = fma(R(c), u[a], acc);
+    });
+    return acc;
+}
+template <int M, int N, int P, typename R>
+__device__ __forceinline__ R weighted_dot2(const R (&u)[3], const R (&V)[3])
+{
+    R acc = R(0);
+    sfor<0, 3>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        sfor<0, 3>([&](auto B) {
+            constexpr int b = decltype(B)::value;
+            constexpr double c =
+                weight_moment(bump(bump(M, 0, a), 0, b), bump(bump(N, 1, a), 1, b), bump(bump(P, 2, a), 2, b));
+            if constexpr (c != 0.0) acc = fma(R(c) * u[a], V[b], acc);
+        });
+    });
+    return acc;
+}
+
+// The non-orthogonal MRT of Appendix B on one node's deviations d = f - w, in
+// place: raw moments T = M f (Eq. (14)), equilibria T_eq = M f_D^eq of the
+// discrete equilibrium (Sec. II B), Guo forcing G = M R_G,
+//     T* = T - S (T - T_eq) + (I - S/2) G,  f* = M^-1 T*,
+// with the block S of Eq. (13) and u = (sum f e + F/2)/rho.  The raw moments of
+// f_D^eq and R_G are closed forms in the weight moments of D3Q27:
+//   M f_D^eq = rho [ (1 - u^2/(2 c_s^2)) W(e) + W1(u)/c_s^2 + W2(u, u)/(2 c_s^4) ],
+//   M R_G    = (W1(F) - (u.F) W(e))/c_s^2 + W2(u, F)/c_s^4.
+template <typename R>
+__device__ __forceinline__ void collide_mrt(R (&v)[27], R Fx, R Fy, R Fz, const Rates<R> &s)
+{
+    raw_moments(v);  // deviation raw moments T - W
+    const R drho = v[slot(0, 0, 0)];
+    const R rho = R(1) + drho;
+    const R inv_rho = R(1) / rho;
+    const R u[3] = {(v[slot(1, 0, 0)] + R(0.5) * Fx) * inv_rho, (v[slot(0, 1, 0)] + R(0.5) * Fy) * inv_rho,
+                    (v[slot(0, 0, 1)] + R(0.5) * Fz) * inv_rho};
+    const R F[3] = {Fx, Fy, Fz};
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const R uF = u[0] * Fx + u[1] * Fy + u[2] * Fz;
+    R neq[3], gb[3];
+    sfor<0, 27>([&](auto T) {
+        constexpr int t = decltype(T)::value;
+        constexpr int m = sa(t), n = sb(t), p = sc(t);
+        constexpr int ones = (m == 1) + (n == 1) + (p == 1);
+        constexpr int order = m + n + p;
+        if constexpr (order == 0) {
+            // mass is conserved
+        } else if constexpr (order == 1) {
+            v[t] += m == 1 ? Fx : (n == 1 ? Fy : Fz);  // T* = T + F for any s1
+        } else {
+            constexpr R W = R(weight_moment(m, n, p));
+            // equilibrium minus W: rho (3 W1 + 4.5 W2 - 1.5 u^2 W) + drho W
+            R teq = fma(R(3), weighted_dot1<m, n, p>(u), R(4.5) * weighted_dot2<m, n, p>(u, u));
+            if constexpr (W != R(0)) teq = fma(R(-1.5) * uu, W, teq);
+            teq *= rho;
+            if constexpr (W != R(0)) teq = fma(drho, W, teq);
+            R g = fma(R(3), weighted_dot1<m, n, p>(F), R(9) * weighted_dot2<m, n, p>(u, F));
+            if constexpr (W != R(0)) g = fma(R(-3) * uF, W, g);
+            if constexpr (order == 2 && ones == 0) {
+                constexpr int b = m == 2 ? 0 : (n == 2 ? 1 : 2);
+                neq[b] = v[t] - teq;
+                gb[b] = g;
+            } else {
+                constexpr int k = rate_of(m, n, p);
+                const R out = fma(-s.s[k], v[t] - teq, v[t]);
+                v[t] = fma(s.hs[k], g, out);
+            }
+        }
+    });
+    // block of Eq. (13) on (k200, k020, k002), for both the relaxation and (I - S/2) G
+    const R nsum = s.sm * (neq[0] + neq[1] + neq[2]);
+    const R gsum = s.sm * (gb[0] + gb[1] + gb[2]);
+    constexpr int ib[3] = {slot(2, 0, 0), slot(0, 2, 0), slot(0, 0, 2)};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const R sg = fma(s.s[R_S2], gb[b], gsum);
+        v[ib[b]] = v[ib[b]] - fma(s.s[R_S2], neq[b], nsum) + gb[b] - R(0.5) * sg;
+    }
+    inverse_raw_moments(v);
+}
+
+// Deviation of the discrete equilibrium f_D^eq (Sec. II B) from w, per slot:
+// w [drho (1 + ...) + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2].
+template <typename R>
+__device__ __forceinline__ void discrete_equilibrium_dev(R (&v)[27], R drho, R ux, R uy, R uz)
+{
+    const R uu = ux * ux + uy * uy + uz * uz;
+    sfor<0, 27>([&](auto T) {
+        constexpr int t = decltype(T)::value;
+        const R eu = R(sa(t) - 1) * ux + R(sb(t) - 1) * uy + R(sc(t) - 1) * uz;
+        const R poly = fma(R(3), eu, fma(R(4.5) * eu, eu, R(-1.5) * uu));
+        v[t] = weight_of_slot<R>(t) * fma(drho, R(1) + poly, poly);
+    });
 }
 
 // Deviation of the generalized equilibrium (Sec. II B) in central-moment space:

@@ -53,13 +53,14 @@ def test_library_exports_every_declared_symbol():
 def test_desc_layout_matches_header():
     from paper_1801_04586_amd.clbm import Desc
 
-    assert ctypes.sizeof(Desc) == 160
+    assert ctypes.sizeof(Desc) == 312
     assert Desc.s.offset == 32 and Desc.force.offset == 144 and Desc.solid.offset == 152
+    assert Desc.collision.offset == 160 and Desc.wall_velocity.offset == 168
 
 
 def test_strerror_and_version():
     L = _lib()
-    assert L.clbm_abi_version() == 2
+    assert L.clbm_abi_version() == 3
     for code, word in [(0, b"success"), (1, b"invalid"), (2, b"rate"), (3, b"storage"), (4, b"HIP"),
                        (5, b"non-finite")]:
         assert word in L.clbm_strerror(code)
@@ -92,6 +93,9 @@ def _desc(**kw):
     (dict(rates=[1.0, 1.0, 1.5, 1.0, 0.0] + [1.0] * 5), 2, "s3"),
     (dict(rates=[1.0] * 9 + [float("nan")]), 2, "s6"),
     (dict(force=(0.0, float("inf"), 0.0)), 1, "force"),
+    (dict(collision="mrt", lattice="d3q19"), 1, "MRT"),
+    (dict(wall_velocity={(0, 1): (0.1, 0.0, 0.0)}), 1, "periodic"),
+    (dict(wall_velocity={(1, 1): (float("nan"), 0.0, 0.0)}), 1, "wall velocity"),
 ])
 def test_create_rejects_bad_descriptions_before_any_hip_call(kw, code, word):
     rc, h, msg = _create(_desc(**kw))
@@ -107,6 +111,12 @@ def test_create_rejects_bad_storage_and_lattice():
         d.lattice = lat
         rc, h, msg = _create(d)
         assert rc == 1 and h.value is None and "lattice" in msg
+    d = _desc()
+    d.collision = 5
+    assert _create(d)[0] == 1
+    d = _desc()
+    d.reserved = 1
+    assert _create(d)[0] == 1
     assert _create(None)[0] == 1
 
 
