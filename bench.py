@@ -206,6 +206,7 @@ def main():
             "nu": nu,
             "boundaries": "periodic",
             "bytes_per_node": bpn,
+            "plane_stride": lat.P,
         },
         "roofline": {
             "bound": "hbm",
@@ -233,6 +234,19 @@ def main():
     if args.primary_only:
         print(json.dumps(result), flush=True)
         return
+
+    # the same workload with dense planes (plane stride = N, a power of two here)
+    ld = Lattice(dims, (0, 0, 0), "f32", rates, force_field=F32_dev, device=dev, plane_stride=0)
+    ld.init(None, u0_dev)
+    ld.step(4)
+    msd = time_steps(torch, ld, 10)
+    ld.set_fused_steps(False)
+    msd1 = time_steps(torch, ld, 10)
+    result["dense_planes"] = {"plane_stride": ld.P, "fused_mlups": round(nodes / (msd * 1e-3) / 1e6, 1),
+                              "single_step_mlups": round(nodes / (msd1 * 1e-3) / 1e6, 1)}
+    log(f"[bench] dense planes: {result['dense_planes']}")
+    ld.close()
+    del ld
 
     lat.close()
     del lat
@@ -264,6 +278,23 @@ def main():
             lv.close()
             del lv
             torch.cuda.empty_cache()
+        # the raw-moment MRT of Appendix B (Guo forcing) on the same lattice and force field, FP32
+        lv = Lattice(dims, (0, 0, 0), "f32", rates, force_field=F32_dev, device=dev, collision="mrt")
+        lv.init(None, u0_dev)
+        lv.step(4)
+        ms = time_steps(torch, lv, 10)
+        lv.set_fused_steps(False)
+        ms1 = time_steps(torch, lv, 10)
+        b = bytes_per_node("f32", True, False)
+        variants[f"kolmogorov_{L}_mrt_f32"] = {
+            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4), "launch": "two fused steps",
+            "single_step_mlups": round(nodes / (ms1 * 1e-3) / 1e6, 1), "bytes_per_node": b,
+            "frac": round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"[bench] MRT f32: {variants[f'kolmogorov_{L}_mrt_f32']}")
+        lv.close()
+        del lv
+        torch.cuda.empty_cache()
+
         # the D3Q19 scheme of Appendix A on the same lattice and force field
         for storage in ("f32", "f64", "f16"):
             field = F32_dev if storage != "f64" else F64_dev
@@ -285,6 +316,49 @@ def main():
                                            "frac": round(achieved / HBM_PEAK_GBS, 4)}
         f64k = variants[f"kolmogorov_{L}_f64"]["kernel_ms"]
         result["speedup_f32_over_f64"] = round(f64k / step_ms, 3)
+
+        # lid-driven cavity 256^3 (all walls, lid moving with U = 0.1), cascaded and MRT, FP32: the walled path
+        cdims = (256, 256, 256)
+        for coll in ("cascaded", "mrt"):
+            lv = Lattice(cdims, (1, 1, 1), "f32", workloads.rates(0.1 * 256 / 400.0), device=dev, collision=coll,
+                         wall_velocity={(1, 1): (0.1, 0.0, 0.0)})
+            lv.init()
+            lv.step(3)
+            ms = time_steps(torch, lv, 10)
+            b = bytes_per_node("f32", False, False)
+            variants[f"cavity_256_{coll}_f32"] = {
+                "mlups": round(256 ** 3 / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4), "bytes_per_node": b,
+                "frac": round(b * 256 ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log(f"[bench] cavity {coll}: {variants[f'cavity_256_{coll}_f32']}")
+            lv.close()
+            del lv
+        torch.cuda.empty_cache()
+
+        # Table I's workload: 10 000 steps of the shear wave on 5 x ny x 5, the cascaded scheme against
+        # the SRT (BGK) LBM with the discrete equilibrium -- the MRT with every rate equal -- in FP64
+        table1 = {}
+        for ny in (101, 201, 401):
+            sdims = (5, ny, 5)
+            phi = 2 * np.pi / ny
+            us = np.zeros((3, 5, ny, 5))
+            us[0] = (1e-3 * np.sin(phi * np.arange(ny)))[None, :, None]
+            us[1] = 0.3 / np.sqrt(3.0)
+            row = {}
+            for name, coll, r in (("t_C", "cascaded", workloads.rates(0.05)),
+                                  ("t_S", "mrt", np.full(10, workloads.s2_from_nu(0.05)))):
+                lv = Lattice(sdims, (0, 0, 0), "f64", r, device=dev, collision=coll)
+                lv.init(None, us)
+                lv.step(100)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lv.step(10000)
+                torch.cuda.synchronize()
+                row[name] = round(time.perf_counter() - t0, 5)
+                lv.close()
+            row["t_C/t_S"] = round(row["t_C"] / row["t_S"], 3)
+            table1[f"5x{ny}x5"] = row
+        variants["table_I_shear_wave_10000_steps_f64"] = table1
+        log(f"[bench] Table I workload: {table1}")
 
         # plain kernel on the 128^3 Taylor-Green case
         tdims = (128, 128, 128)
@@ -446,6 +520,8 @@ def main():
 
     result["context"] = {
         "paper_cpu": "0.45 MLUPS: C++ CLBM, i7-6500U laptop, 5x101x5 shear wave (Table I), context only",
+        "paper_table_I_seconds": {"5x101x5": [56.028, 26.042, 2.151], "5x201x5": [111.838, 51.728, 2.162],
+                                  "5x401x5": [217.027, 101.179, 2.145], "columns": "t_C, t_S, t_C/t_S (CPU)"},
         "hbm_peak_gbs": HBM_PEAK_GBS,
     }
     print(json.dumps(result), flush=True)

@@ -23,7 +23,7 @@ STORAGE_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float1
 # arithmetic / adjoint / force-field type per storage
 REAL_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float32, "bf16": torch.float32}
 RATE_NAMES = ("s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6")
-ABI_VERSION = 3  # CLBM_ABI_VERSION of include/clbm.h
+ABI_VERSION = 4  # CLBM_ABI_VERSION of include/clbm.h
 CLBM_D3Q27, CLBM_D3Q19 = 0, 1
 LATTICE = {"d3q27": CLBM_D3Q27, "d3q19": CLBM_D3Q19}
 LATTICE_Q = {"d3q27": 27, "d3q19": 19}
@@ -53,6 +53,7 @@ class Desc(ctypes.Structure):
         ("collision", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("wall_velocity", ctypes.c_double * 18),
+        ("plane_stride", ctypes.c_int64),
     ]
 
 
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH):
     vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
     sig = {
         "clbm_abi_version": ([], ctypes.c_int),
+        "clbm_default_plane_stride": ([i32, i32, i32, i32], ctypes.c_int64),
         "clbm_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clbm_last_error": ([vp], ctypes.c_char_p),
         "clbm_create": ([ctypes.POINTER(vp), ctypes.POINTER(Desc), vp], ctypes.c_int),
@@ -128,6 +130,19 @@ class Context:
         if rc:
             raise ClbmError("clbm_create", rc, self.lib.clbm_last_error(None).decode())
         self.desc = desc
+        n = desc.nx * desc.ny * desc.nz
+        q = 19 if desc.lattice == CLBM_D3Q19 else 27
+        es = {CLBM_F64: 8, CLBM_F32: 4}.get(desc.storage, 2)
+        self.state_bytes = q * (desc.plane_stride or n) * es  # size of one state buffer
+
+    def _state(self, t: Optional[torch.Tensor]):
+        """Pointer of a state buffer, after checking that it holds Q x P elements of the storage type."""
+        if t is None:
+            raise ValueError("state buffer is None")
+        if t.numel() * t.element_size() < self.state_bytes:
+            raise ValueError(f"state buffer of {t.numel() * t.element_size()} bytes, {self.state_bytes} needed "
+                             "(Q x plane_stride elements)")
+        return _ptr(t)
 
     def _call(self, name, *args):
         fn = getattr(self.lib, name)
@@ -158,29 +173,29 @@ class Context:
         self._call("clbm_set_force", u, _ptr(field), ctypes.c_double(float(scale)))
 
     def init(self, state, rho0=None, u0=None):
-        self._call("clbm_init", _ptr(state), _ptr(rho0), _ptr(u0))
+        self._call("clbm_init", self._state(state), _ptr(rho0), _ptr(u0))
 
     def step(self, src, dst):
-        self._call("clbm_step", _ptr(src), _ptr(dst))
+        self._call("clbm_step", self._state(src), self._state(dst))
 
     def run(self, a, b, nsteps: int) -> bool:
         """Runs nsteps; returns True when the final state is in b."""
         res = ctypes.c_void_p()
-        self._call("clbm_run", _ptr(a), _ptr(b), ctypes.c_int32(int(nsteps)), ctypes.byref(res))
+        self._call("clbm_run", self._state(a), self._state(b), ctypes.c_int32(int(nsteps)), ctypes.byref(res))
         return res.value == b.data_ptr()
 
     def set_options(self, options: int):
         self._call("clbm_set_options", ctypes.c_uint32(int(options)))
 
     def copy(self, src, dst):
-        self._call("clbm_copy", _ptr(src), _ptr(dst))
+        self._call("clbm_copy", self._state(src), self._state(dst))
 
     def moments(self, state, rho=None, u=None, want_totals=True):
         totals = (ctypes.c_double * 4)() if want_totals else None
         nbad = ctypes.c_int64(0) if want_totals else None
         fn = self.lib.clbm_moments
         self.lib.clbm_set_stream(self._h, _stream(self.device))
-        rc = fn(self._h, _ptr(state), _ptr(rho), _ptr(u), totals, ctypes.byref(nbad) if want_totals else None)
+        rc = fn(self._h, self._state(state), _ptr(rho), _ptr(u), totals, ctypes.byref(nbad) if want_totals else None)
         if rc and rc != 5:
             raise ClbmError("clbm_moments", rc, self.lib.clbm_last_error(self._h).decode())
         if not want_totals:
@@ -188,20 +203,20 @@ class Context:
         return np.array(list(totals)), int(nbad.value)
 
     def get_populations(self, state, out):
-        self._call("clbm_get_populations", _ptr(state), _ptr(out))
+        self._call("clbm_get_populations", self._state(state), _ptr(out))
 
     def set_populations(self, f, state):
-        self._call("clbm_set_populations", _ptr(f), _ptr(state))
+        self._call("clbm_set_populations", _ptr(f), self._state(state))
 
     def sample_populations(self, state, nodes, out):
-        self._call("clbm_sample_populations", _ptr(state), _ptr(nodes), ctypes.c_int32(int(nodes.numel())),
+        self._call("clbm_sample_populations", self._state(state), _ptr(nodes), ctypes.c_int32(int(nodes.numel())),
                    _ptr(out))
 
     def adjoint_step(self, state_t, lam_next, lam_out, dJdF=None, dJds=None):
-        self._call("clbm_adjoint_step", _ptr(state_t), _ptr(lam_next), _ptr(lam_out), _ptr(dJdF), _ptr(dJds))
+        self._call("clbm_adjoint_step", self._state(state_t), _ptr(lam_next), _ptr(lam_out), _ptr(dJdF), _ptr(dJds))
 
     def loss_seed(self, state, u_target, lam_out, dJdF=None, J=None):
-        self._call("clbm_loss_seed", _ptr(state), _ptr(u_target), _ptr(lam_out), _ptr(dJdF), _ptr(J))
+        self._call("clbm_loss_seed", self._state(state), _ptr(u_target), _ptr(lam_out), _ptr(dJdF), _ptr(J))
 
 
 def wall_velocity_array(wall_velocity) -> np.ndarray:
@@ -217,9 +232,20 @@ def wall_velocity_array(wall_velocity) -> np.ndarray:
     return np.asarray(wall_velocity, dtype=np.float64).reshape(6, 3).copy()
 
 
+def default_plane_stride(dims, storage) -> int:
+    """clbm_default_plane_stride: N rounded up to 256 B plus 4 KiB, in elements."""
+    nx, ny, nz = (int(v) for v in dims)
+    P = load_library().clbm_default_plane_stride(nx, ny, nz, STORAGE[storage])
+    if P < 0:
+        raise ValueError("invalid lattice dims or storage")
+    return int(P)
+
+
 def make_desc(dims, walls=(0, 0, 0), storage="f32", rates=None, force=(0.0, 0.0, 0.0), force_field=None,
-              force_scale=1.0, solid=None, lattice="d3q27", collision="cascaded", wall_velocity=None) -> Desc:
+              force_scale=1.0, solid=None, lattice="d3q27", collision="cascaded", wall_velocity=None,
+              plane_stride=0) -> Desc:
     d = Desc()
+    d.plane_stride = int(plane_stride)
     d.collision = COLLISION[collision]
     d.reserved = 0
     for k, v in enumerate(wall_velocity_array(wall_velocity).reshape(18)):
@@ -259,12 +285,17 @@ class Lattice:
     it (times force_scale); solid = (nz, ny, nx) mask, nonzero = solid;
     lattice = "d3q27" (Eq. (1)) or "d3q19" (Appendix A); collision = "cascaded"
     (Sec. II) or "mrt" (the raw-moment MRT of Appendix B, D3Q27); wall_velocity =
-    moving wall faces, {(axis, side): (ux, uy, uz)} (side 1 beyond n - 1).
+    moving wall faces, {(axis, side): (ux, uy, uz)} (side 1 beyond n - 1);
+    plane_stride = plane stride P of the state buffers (None: the library's
+    default, N plus a little padding; 0: P = N).
+
+    State buffers are contiguous (Q, P) tensors whose padding is zero; view()
+    gives the (Q, nz, ny, nx) part that holds the lattice.
     """
 
     def __init__(self, dims: Sequence[int], walls=(0, 0, 0), storage="f32", rates=None, force=(0.0, 0.0, 0.0),
                  force_field=None, force_scale=1.0, solid=None, device=None, lattice="d3q27", collision="cascaded",
-                 wall_velocity=None):
+                 wall_velocity=None, plane_stride=None):
         if not torch.cuda.is_available():
             raise RuntimeError("clbm needs a GPU (HIP); none is visible")
         self.device = torch.device(device if device is not None else "cuda")
@@ -284,15 +315,26 @@ class Lattice:
         self.rates = np.array([1.0] * 10 if rates is None else rates, dtype=np.float64)
         self.force = tuple(float(v) for v in force)
         self.force_scale = float(force_scale)
+        if plane_stride is None:
+            plane_stride = default_plane_stride(self.dims, storage)
+        self.P = int(plane_stride) if plane_stride else self.n
         desc = make_desc(self.dims, self.walls, storage, self.rates, self.force, self.force_field, force_scale,
-                         self.solid, lattice, collision, self.wall_velocity)
+                         self.solid, lattice, collision, self.wall_velocity, plane_stride)
         self.ctx = Context(desc, self.device)
-        self.bufs = [torch.empty((self.q,) + self.shape, dtype=STORAGE_TORCH[storage], device=self.device)
-                     for _ in range(2)]
+        self.bufs = [self.new_state() for _ in range(2)]
         self.cur = 0
         self.t = 0
 
     # ---- state
+    def new_state(self) -> torch.Tensor:
+        """A zeroed state buffer (Q, P) of this lattice."""
+        return torch.zeros((self.q, self.P), dtype=STORAGE_TORCH[self.storage], device=self.device)
+
+    def view(self, t: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The (Q, nz, ny, nx) lattice part of a state buffer (default: the current state)."""
+        t = self.state if t is None else t
+        return t[:, : self.n].view((self.q,) + self.shape)
+
     @property
     def state(self) -> torch.Tensor:
         return self.bufs[self.cur]

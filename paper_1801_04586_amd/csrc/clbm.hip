@@ -81,6 +81,13 @@ int validate_desc(const clbm_desc *d)
     if (d->collision == CLBM_MRT && d->lattice != CLBM_D3Q27)
         return fail(nullptr, CLBM_EINVAL, "the MRT collision needs the D3Q27 lattice");
     if (d->reserved != 0) return fail(nullptr, CLBM_EINVAL, "reserved field must be 0");
+    if (d->plane_stride != 0) {
+        const size_t es = d->storage == CLBM_F64 ? 8 : (d->storage == CLBM_F32 ? 4 : 2);
+        if (d->plane_stride < n || d->plane_stride > 0xffffffffll)
+            return fail(nullptr, CLBM_EINVAL, "plane_stride must lie in [nx*ny*nz, 2^32)");
+        if ((static_cast<size_t>(d->plane_stride) * es) % 16 != 0)
+            return fail(nullptr, CLBM_EINVAL, "plane_stride * element size must be a multiple of 16 bytes");
+    }
     for (int f = 0; f < 6; ++f)
         for (int b = 0; b < 3; ++b) {
             const double w = d->wall_velocity[f][b];
@@ -264,6 +271,16 @@ extern "C" {
 
 int clbm_abi_version(void) { return CLBM_ABI_VERSION; }
 
+int64_t clbm_default_plane_stride(int32_t nx, int32_t ny, int32_t nz, int32_t storage)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || storage < CLBM_F64 || storage > CLBM_BF16) return -1;
+    const long long n = static_cast<long long>(nx) * ny * nz;
+    if (n >= (1ll << 31)) return -1;
+    const long long es = static_cast<long long>(store_size(storage));
+    const long long align = 256 / es, pad = 4096 / es;
+    return (n + align - 1) / align * align + pad;
+}
+
 const char *clbm_strerror(int status)
 {
     switch (status) {
@@ -296,6 +313,7 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
     g.nz = desc->nz;
     g.nxy = g.nx * g.ny;
     g.N = static_cast<uint32_t>(c->nodes);
+    g.P = desc->plane_stride ? static_cast<uint32_t>(desc->plane_stride) : g.N;
     g.dnx.init(g.nx);
     g.dny.init(g.ny);
     for (int a = 0; a < 3; ++a) g.wall[a] = desc->wall[a];
@@ -459,7 +477,7 @@ int clbm_copy(clbm_ctx *ctx, const void *src, void *dst)
     if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
     if (!src || !dst || !aligned(src) || !aligned(dst) || src == dst)
         return fail(ctx, CLBM_EINVAL, "bad copy buffers");
-    const size_t bytes = ctx->nodes * lattice_q(ctx->d) * store_size(ctx->d.storage);
+    const size_t bytes = static_cast<size_t>(ctx->geom.P) * lattice_q(ctx->d) * store_size(ctx->d.storage);
     const size_t n16 = bytes / 16, tail = bytes % 16;
     if (n16) {
         size_t blocks = (n16 + kBlock - 1) / kBlock;

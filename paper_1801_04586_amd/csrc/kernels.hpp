@@ -1,7 +1,8 @@
 // HIP kernels of the D3Q27 cascaded LBM for gfx950 (MI355X).
 //
-// Memory layout: a state is [27][N] in the storage type (structure of arrays,
-// x fastest), so a wavefront of 64 lanes on 64 consecutive nodes reads and
+// Memory layout: a state is [27][P] in the storage type (structure of arrays,
+// x fastest; plane stride P >= N, the first N entries of a plane used), so a
+// wavefront of 64 lanes on 64 consecutive nodes reads and
 // writes 64 consecutive elements of each population plane.  The step is a
 // "pull" step: node x gathers population i from x - e_i of the previous
 // post-collision state (Eq. (8) read backwards), collides in registers and
@@ -82,6 +83,7 @@ struct FastDiv {
 
 struct Geom {
     uint32_t N, nx, ny, nz, nxy;
+    uint32_t P;        // plane stride of state buffers in elements (>= N; padding breaks power-of-two strides)
     FastDiv dnx, dny;
     int32_t wall[3];
     int32_t moving;    // some wall face moves
@@ -235,7 +237,9 @@ template <typename S, bool CHECK, bool SOLID, bool REV, int Q, typename R>
 __device__ __forceinline__ void gather_links(const S *__restrict__ buf, const Geom &g, uint32_t n, const Nbr &nb,
                                              uint32_t lm, R (&v)[27])
 {
-    const uint32_t N = g.N;
+    // forward gathers read state buffers (plane stride P); reverse gathers read
+    // adjoint buffers, which are dense [27][N]
+    const size_t N = REV ? static_cast<size_t>(g.N) : static_cast<size_t>(g.P);
     constexpr uint32_t es = sizeof(S);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
@@ -270,7 +274,7 @@ template <typename S, bool CHECK, bool SOLID, int Q, typename R>
 __device__ __forceinline__ void scatter(S *__restrict__ buf, const Geom &g, uint32_t n, const Nbr &nb, uint32_t lm,
                                         const R (&v)[27])
 {
-    const uint32_t N = g.N;
+    const size_t N = g.P;  // state buffer
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         constexpr int i = pop_of_slot(t);
@@ -456,7 +460,7 @@ __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src,
         if constexpr (has_slot<Q>(t)) {
             R val = v[t];
             if constexpr (!Traits<S>::kDev) val += lattice_weight<Q, R>(t);
-            store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.N, nb_off, to_store<S>(val));
+            store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.P, nb_off, to_store<S>(val));
         }
     });
 }
@@ -552,7 +556,7 @@ __global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S
             constexpr int t = decltype(TT)::value;
             uint32_t off;
             link_open<t, false, false>(nb, 0u, off);
-            pre[t] = load_at(src + static_cast<size_t>(pop_of_slot(t)) * g.N, off * es);
+            pre[t] = load_at(src + static_cast<size_t>(pop_of_slot(t)) * g.P, off * es);
         });
         load_field<FIELD>(field, g.N, n, pFx, pFy, pFz);  // raw values: combined only when used
     };
@@ -591,7 +595,7 @@ __global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S
         const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
         sfor<0, 27>([&](auto TT) {
             constexpr int t = decltype(TT)::value;
-            store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.N, nb_off, to_store<S>(v[t]));
+            store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.P, nb_off, to_store<S>(v[t]));
         });
     };
 

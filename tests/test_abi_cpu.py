@@ -53,14 +53,25 @@ def test_library_exports_every_declared_symbol():
 def test_desc_layout_matches_header():
     from paper_1801_04586_amd.clbm import Desc
 
-    assert ctypes.sizeof(Desc) == 312
+    assert ctypes.sizeof(Desc) == 320
     assert Desc.s.offset == 32 and Desc.force.offset == 144 and Desc.solid.offset == 152
-    assert Desc.collision.offset == 160 and Desc.wall_velocity.offset == 168
+    assert Desc.collision.offset == 160 and Desc.wall_velocity.offset == 168 and Desc.plane_stride.offset == 312
+
+
+def test_default_plane_stride():
+    """N rounded up to 256 bytes plus 4 KiB, in elements of the storage type; -1 for bad input."""
+    L = _lib()
+    assert L.clbm_default_plane_stride(512, 512, 512, 1) == 512 ** 3 + 1024
+    assert L.clbm_default_plane_stride(7, 6, 5, 0) == 224 + 512
+    assert L.clbm_default_plane_stride(7, 6, 5, 2) == 256 + 2048
+    assert L.clbm_default_plane_stride(0, 6, 5, 1) == -1
+    assert L.clbm_default_plane_stride(4, 4, 4, 9) == -1
+    assert L.clbm_default_plane_stride(2048, 2048, 1024, 1) == -1
 
 
 def test_strerror_and_version():
     L = _lib()
-    assert L.clbm_abi_version() == 3
+    assert L.clbm_abi_version() == 4
     for code, word in [(0, b"success"), (1, b"invalid"), (2, b"rate"), (3, b"storage"), (4, b"HIP"),
                        (5, b"non-finite")]:
         assert word in L.clbm_strerror(code)
@@ -96,6 +107,8 @@ def _desc(**kw):
     (dict(collision="mrt", lattice="d3q19"), 1, "MRT"),
     (dict(wall_velocity={(0, 1): (0.1, 0.0, 0.0)}), 1, "periodic"),
     (dict(wall_velocity={(1, 1): (float("nan"), 0.0, 0.0)}), 1, "wall velocity"),
+    (dict(plane_stride=63), 1, "plane_stride"),
+    (dict(plane_stride=66), 1, "16 bytes"),
 ])
 def test_create_rejects_bad_descriptions_before_any_hip_call(kw, code, word):
     rc, h, msg = _create(_desc(**kw))

@@ -60,7 +60,7 @@ def test_state_has_19_planes_and_init_is_the_equilibrium():
     ref = oracle.init(g, rho0, u0, lattice=Q19)
     for storage, tol in (("f64", 1e-15), ("f32", 1e-9)):
         lat = _lattice(dims, walls, storage)
-        assert lat.state.shape == (19, 7, 8, 9)
+        assert lat.view().shape == (19, 7, 8, 9) and lat.state.shape == (19, lat.P)
         lat.init(rho0, u0)
         got = lat.populations().cpu().numpy()
         assert np.max(np.abs(got - ref)) < tol, storage

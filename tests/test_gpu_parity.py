@@ -231,9 +231,33 @@ def test_every_fluid_entry_is_written(storage):
     lat.set_populations(torch.from_numpy(f0))
     lat.other.fill_(float("nan"))
     lat.step(1)
-    st = lat.state.to(torch.float64).cpu().numpy()
+    st = lat.view().to(torch.float64).cpu().numpy()
     assert not np.isnan(st[:, solid == 0]).any()
     lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_plane_stride_changes_nothing_but_the_layout(storage):
+    """The default padded plane stride and a dense one (P = N) give identical results, and the
+    padding is never written."""
+    from paper_1801_04586_amd import Lattice
+
+    dims, walls = (21, 13, 7), (0, 1, 1)
+    solid = workloads.random_solids(dims, 0.1, 111)
+    g, f0 = _random_start(dims, walls, 112)
+    field = workloads.gaussian_force(dims, 1e-4, 113)
+    out = []
+    for ps in (None, 0):
+        lat = Lattice(dims, walls, storage, RATES, force=(1e-5, 0, 0), force_field=field, solid=solid,
+                      plane_stride=ps)
+        assert (lat.P > lat.n) == (ps is None)
+        lat.set_populations(torch.from_numpy(f0))
+        lat.step(7)
+        out.append(lat.populations().cpu().numpy())
+        for b in lat.bufs:
+            assert torch.count_nonzero(b[:, lat.n:]).item() == 0
+        lat.close()
+    assert np.array_equal(out[0], out[1])
 
 
 def test_runs_are_bitwise_deterministic():
