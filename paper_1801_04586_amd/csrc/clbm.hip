@@ -75,6 +75,11 @@ int validate_desc(const clbm_desc *d)
     for (int a = 0; a < 3; ++a)
         if (d->wall[a] != 0 && d->wall[a] != 1) return fail(nullptr, CLBM_EINVAL, "wall flags must be 0 or 1");
     if (d->storage < CLBM_F64 || d->storage > CLBM_BF16) return fail(nullptr, CLBM_EDTYPE, "unknown storage type");
+    // kernels address a plane (state, adjoint, force field: elements of at most 8 bytes for FP64
+    // storage, 4 otherwise) with 32-bit byte offsets
+    const long long widest = d->storage == CLBM_F64 ? 8 : 4;
+    if (n * widest > (1ll << 32))
+        return fail(nullptr, CLBM_EINVAL, "lattice too large: nx*ny*nz times the element size must not exceed 4 GiB");
     if (d->lattice != CLBM_D3Q27 && d->lattice != CLBM_D3Q19) return fail(nullptr, CLBM_EINVAL, "unknown lattice");
     if (d->collision != CLBM_CASCADED && d->collision != CLBM_MRT)
         return fail(nullptr, CLBM_EINVAL, "unknown collision model");

@@ -108,6 +108,8 @@ def _desc(**kw):
     (dict(wall_velocity={(0, 1): (0.1, 0.0, 0.0)}), 1, "periodic"),
     (dict(wall_velocity={(1, 1): (float("nan"), 0.0, 0.0)}), 1, "wall velocity"),
     (dict(plane_stride=63), 1, "plane_stride"),
+    (dict(dims=(1024, 1024, 513), storage="f64"), 1, "too large"),
+    (dict(dims=(1024, 1024, 1025), storage="f16"), 1, "too large"),
     (dict(plane_stride=66), 1, "16 bytes"),
 ])
 def test_create_rejects_bad_descriptions_before_any_hip_call(kw, code, word):
