@@ -227,14 +227,16 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
     });
 }
 
-// Two fused steps per launch apply to periodic lattices without solids with FP32
-// storage.  FP64 does not fit the LDS ring at this tile size, and for 16-bit
-// storage (half the bytes of FP32) the single-step kernel is faster: the fused
-// kernel's cost per step is set by its arithmetic and barriers, not by memory.
+// Two fused steps per launch apply to periodic D3Q27 lattices without solids with
+// FP32 storage and the cascaded collision.  FP64 does not fit the LDS groups at
+// this tile size; for 16-bit storage (half the bytes of FP32) the single-step
+// kernel is faster, the fused kernel's cost per step being set by its arithmetic
+// and barriers rather than by memory; and the MRT's larger register footprint
+// leaves the fused kernel two blocks per CU, slower than single steps.
 bool fused_pairs(const clbm_ctx *c)
 {
     return !(c->options & CLBM_OPT_SINGLE_STEP) && c->d.lattice == CLBM_D3Q27 && c->d.storage == CLBM_F32 &&
-           !c->links && !c->d.wall[0] && !c->d.wall[1] && !c->d.wall[2];
+           c->d.collision == CLBM_CASCADED && !c->links && !c->d.wall[0] && !c->d.wall[1] && !c->d.wall[2];
 }
 
 int launch_step2(clbm_ctx *c, const void *src, void *dst)
@@ -263,7 +265,6 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
                                static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
             return check_launch(c, "fused two-step kernel launch");
         };
-        if (coll == kMrt) return launch(std::integral_constant<int, kMrt>{});
         if (coll == kCascadedHigh1) return launch(std::integral_constant<int, kCascadedHigh1>{});
         return launch(std::integral_constant<int, kCascaded>{});
     };

@@ -491,12 +491,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 // type exactly as a stored state would be, so the result is bitwise that of
 // two single steps.
 //
-// LDS ring: step t+2 at plane z pulls the e_z = -1 populations from plane z+1,
-// e_z = 0 from plane z and e_z = +1 from plane z-1 of the intermediate state.
-// Grouped by e_z, a plane's 9 populations with e_z = -1 are needed for one
-// plane iteration, those with e_z = 0 for two and those with e_z = +1 for
-// three, so the ring holds 1 + 2 + 3 plane slots of 9 x 340 values (73 KB,
-// two blocks per CU).
+// LDS: step t+2 at plane z pulls the e_z = -1 populations from plane z+1, e_z = 0
+// from plane z and e_z = +1 from plane z-1 of the intermediate state.  Each
+// thread keeps its halo node's e_z = 0 group for one plane iteration and its
+// e_z = +1 group for two in registers and writes a group to LDS only in the
+// iteration that pulls it, so LDS holds just three groups of 9 x 340 values
+// (37 KB): three blocks (18 waves) fit on a CU, limited by the 87 VGPRs.
 constexpr int kT2X = 32, kT2Y = 8;
 constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 340 nodes
 constexpr int kT2Block = 384;                                               // >= kT2H, six wavefronts
@@ -511,14 +511,16 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
     return static_cast<uint32_t>(r < 0 ? r + static_cast<int>(n) : r);
 }
 
+// (the waves-per-EU bound keeps the register budget at or below 128)
 template <typename S, bool FIELD, int COLL>
-__global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg,
-                                                    const typename Traits<S>::R *__restrict__ field,
-                                                    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
+__global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) void k_step2(
+    const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const typename Traits<S>::R *__restrict__ field,
+    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
 {
     using R = typename Traits<S>::R;
     static_assert(std::is_same<R, float>::value, "the LDS ring holds FP32 values");
-    __shared__ float ring[6][9][kT2H];  // [0]: e_z=-1 (1 slot), [1..2]: e_z=0 (2 slots), [3..5]: e_z=+1 (3 slots)
+    // [0]: e_z = -1 group of plane z+1, [1]: e_z = 0 group of plane z, [2]: e_z = +1 group of plane z-1
+    __shared__ float ring[3][9][kT2H];
 
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t tx = b % tg.tiles_x, rest = b / tg.tiles_x;
@@ -528,55 +530,39 @@ __global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S
     const int z1 = min(z0 + static_cast<int>(tg.zchunk), static_cast<int>(g.nz));
     const int tid = threadIdx.x;
 
-    // step t -> t+1 role: halo node (hx, hy)
     const bool ha = tid < kT2H;
     const int hx = tid % kT2HX, hy = tid / kT2HX;
     const uint32_t gx = wrap_coord(x0 - 1 + hx, g.nx), gy = wrap_coord(y0 - 1 + hy, g.ny);
-    // step t+1 -> t+2 role: tile node (cx, cy)
     const int cx = tid % kT2X, cy = tid / kT2X;
     const bool ca = tid < kT2X * kT2Y && x0 + cx < static_cast<int>(g.nx) && y0 + cy < static_cast<int>(g.ny);
 
-    // ring slot of plane p (unwrapped) for the group with e_z index c = e_z + 1
-    auto ring_slot = [&](int c, int p) {
-        const int q = p - z0 + 1;  // >= 0 for every plane touched
-        return c == 0 ? 0 : (c == 1 ? 1 + (q & 1) : 3 + q % 3);
-    };
+    // groups of the halo node's intermediate values kept in registers until the plane that pulls
+    // them: e_z = 0 of plane p, e_z = +1 of planes p - 1 and p (p: the last plane computed)
+    float keep0[9], keep2a[9], keep2b[9];
 
-    // The first step is split into its loads (into registers) and its arithmetic, so
-    // that the loads of plane p+1 are in flight while the block works on plane p.
-    // prefetched values stay in the storage type: a conversion right after the load
-    // would make the wavefront wait for it (and, counters being in order, for all
-    // earlier loads) before the barrier
-    S pre[27];
-    R pFx = R(0), pFy = R(0), pFz = R(0);
-    auto load_first = [&](int p) {
+    auto first_step = [&](int p) {
         if (!ha) return;
         const uint32_t pz = wrap_coord(p, g.nz);
         const uint32_t n = gx + g.nx * (gy + g.ny * pz);
         Nbr nb;
         neighbours_xyz(g, gx, gy, pz, nb);
         constexpr uint32_t es = sizeof(S);
+        R v[27];
         sfor<0, 27>([&](auto TT) {
             constexpr int t = decltype(TT)::value;
             uint32_t off;
             link_open<t, false, false>(nb, 0u, off);
-            pre[t] = load_at(src + static_cast<size_t>(pop_of_slot(t)) * g.P, off * es);
+            v[t] = to_real(load_at(src + static_cast<size_t>(pop_of_slot(t)) * g.P, off * es));
         });
-        load_field<FIELD>(field, g.N, n, pFx, pFy, pFz);  // raw values: combined only when used
-    };
-    auto first_step = [&](int p) {
-        if (!ha) return;
-        R v[27];
-        sfor<0, 27>([&](auto T) { v[decltype(T)::value] = to_real(pre[decltype(T)::value]); });
         R Fx, Fy, Fz;
-        force_from<FIELD>(fo, pFx, pFy, pFz, Fx, Fy, Fz);
+        force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
         node_update<COLL>(v, Fx, Fy, Fz, rt);
-        const int sA = ring_slot(0, p), sB = ring_slot(1, p), sC = ring_slot(2, p);
-        sfor<0, 27>([&](auto TT) {
-            constexpr int t = decltype(TT)::value;
-            constexpr int c = sc(t), j = 3 * sa(t) + sb(t);
-            const float val = static_cast<float>(to_store<S>(v[t]));  // the value a stored state would hold
-            ring[c == 0 ? sA : (c == 1 ? sB : sC)][j][tid] = val;
+        sfor<0, 9>([&](auto J) {
+            constexpr int j = decltype(J)::value;  // j = 3 a + b; slot 3 j + c with c = e_z + 1
+            ring[0][j][tid] = static_cast<float>(to_store<S>(v[3 * j + 0]));  // the value a stored state would hold
+            keep2a[j] = keep2b[j];
+            keep0[j] = static_cast<float>(to_store<S>(v[3 * j + 1]));
+            keep2b[j] = static_cast<float>(to_store<S>(v[3 * j + 2]));
         });
     };
 
@@ -584,14 +570,12 @@ __global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S
         if (!ca) return;
         const uint32_t zz = wrap_coord(z, g.nz);
         const uint32_t n = static_cast<uint32_t>(x0 + cx) + g.nx * (static_cast<uint32_t>(y0 + cy) + g.ny * zz);
-        const int sA = ring_slot(0, z + 1), sB = ring_slot(1, z), sC = ring_slot(2, z - 1);
         R v[27];
         sfor<0, 27>([&](auto TT) {
             constexpr int t = decltype(TT)::value;
             constexpr int a = sa(t), bb = sb(t), c = sc(t), j = 3 * a + bb;
-            // pull from (x - e_x, y - e_y) of the halo tile, e = (a - 1, b - 1)
             const int h = (cy + 2 - bb) * kT2HX + (cx + 2 - a);
-            v[t] = ring[c == 0 ? sA : (c == 1 ? sB : sC)][j][h];
+            v[t] = ring[c][j][h];
         });
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
@@ -603,16 +587,19 @@ __global__ __launch_bounds__(kT2Block) void k_step2(const S *__restrict__ src, S
         });
     };
 
-    load_first(z0 - 1);
-    first_step(z0 - 1);
-    load_first(z0);
-    first_step(z0);
-    load_first(z0 + 1);
+    sfor<0, 9>([&](auto J) { keep2b[decltype(J)::value] = 0.0f; });
+    first_step(z0 - 1);  // keep2b <- e_z = +1 group of plane z0 - 1
+    first_step(z0);      // keep0 <- e_z = 0 of z0, keep2a <- +1 of z0 - 1, keep2b <- +1 of z0
     for (int z = z0; z < z1; ++z) {
         __syncthreads();  // the previous plane's pulls from the ring are done
-        first_step(z + 1);
-        if (z + 1 < z1) load_first(z + 2);  // in flight during the second step below
-        __syncthreads();  // plane z+1 is in the ring
+        if (ha)
+            sfor<0, 9>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                ring[1][j][tid] = keep0[j];   // e_z = 0 of plane z
+                ring[2][j][tid] = keep2a[j];  // e_z = +1 of plane z - 1
+            });
+        first_step(z + 1);  // ring[0] <- e_z = -1 of plane z + 1
+        __syncthreads();    // the three groups of second_step(z) are in the ring
         second_step(z);
     }
 }
