@@ -219,6 +219,10 @@ def main():
             "kernel_ms": round(kernel_ms, 4),
             "node_updates_per_launch": nodes * (2 if fused else 1),
             "algorithmic_bytes_per_launch": bpn * nodes * (2 if fused else 1),
+            # HBM bytes the kernel actually moves (counter summary) per unit of kernel time; with two
+            # fused steps per launch this is below the algorithmic rate, which counts every update
+            "traffic_gbs": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9, 1),
+            "traffic_frac": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
     }
     if fused:

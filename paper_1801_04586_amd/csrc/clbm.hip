@@ -31,6 +31,8 @@ struct clbm_ctx {
     double *scal;      // [16] reduction results
     uint32_t *links;   // [N] link table (k_links) when the lattice has solid nodes, else NULL
     uint32_t options;  // CLBM_OPT_* flags
+    int num_cu;        // compute units of the device
+    int t2_slots[2][2];  // resident blocks of the fused kernel on the device, by (force field, collision); 0 = unknown
     char err[512];
 };
 
@@ -239,20 +241,35 @@ bool fused_pairs(const clbm_ctx *c)
            c->d.collision == CLBM_CASCADED && !c->links && !c->d.wall[0] && !c->d.wall[1] && !c->d.wall[2];
 }
 
+// A block of the fused kernel runs through a whole z chunk, so a launch whose last
+// round of blocks fills only part of the GPU idles for the rest of that round.
+// Choose the chunks per tile column (each of at least 8 planes) to minimise
+// rounds x (planes per chunk + 2), the two extra planes being the halo planes a
+// chunk recomputes; slots = blocks resident on the device at once.
+uint32_t fused_chunks(uint32_t tiles, uint32_t nz, uint32_t slots)
+{
+    const uint32_t max_chunks = nz / 8 > 1 ? nz / 8 : 1;
+    uint32_t best = 1;
+    unsigned long long best_cost = ~0ull;
+    for (uint32_t nc = 1; nc <= max_chunks; ++nc) {
+        const uint32_t zchunk = (nz + nc - 1) / nc;
+        const uint32_t used = (nz + zchunk - 1) / zchunk;
+        const unsigned long long rounds = (static_cast<unsigned long long>(tiles) * used + slots - 1) / slots;
+        const unsigned long long cost = rounds * (zchunk + 2);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = used;
+        }
+    }
+    return best;
+}
+
 int launch_step2(clbm_ctx *c, const void *src, void *dst)
 {
     T2Geom tg;
     tg.tiles_x = (c->geom.nx + kT2X - 1) / kT2X;
     tg.tiles_y = (c->geom.ny + kT2Y - 1) / kT2Y;
     const uint32_t tiles = tg.tiles_x * tg.tiles_y;
-    // about 2048 blocks (8 per CU) when the lattice allows, chunks of at least 8 planes
-    uint32_t nchunks = (2048 + tiles - 1) / tiles;
-    const uint32_t max_chunks = (c->geom.nz + 7) / 8;
-    if (nchunks > max_chunks) nchunks = max_chunks;
-    if (nchunks < 1) nchunks = 1;
-    tg.zchunk = (c->geom.nz + nchunks - 1) / nchunks;
-    nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
-    const unsigned blocks = tiles * nchunks;
     const int coll = collision_of(c);
     auto go = [&](auto tag, auto field_tag) {
         using S = decltype(tag);
@@ -260,6 +277,18 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         constexpr bool FIELD = decltype(field_tag)::value;
         auto launch = [&](auto cc) {
             constexpr int C = decltype(cc)::value;
+            int &slots = c->t2_slots[FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0];
+            if (slots == 0) {
+                int per_cu = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C>, kT2Block, 0) !=
+                        hipSuccess || per_cu < 1)
+                    per_cu = 1;
+                slots = per_cu * c->num_cu;
+            }
+            const uint32_t nchunks_req = fused_chunks(tiles, c->geom.nz, static_cast<uint32_t>(slots));
+            tg.zchunk = (c->geom.nz + nchunks_req - 1) / nchunks_req;
+            const uint32_t nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
+            const unsigned blocks = tiles * nchunks;
             hipLaunchKernelGGL((k_step2<S, FIELD, C>), dim3(blocks), dim3(kT2Block), 0, c->stream,
                                static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg,
                                static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
@@ -345,6 +374,16 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
     }
     c->links = nullptr;
     c->options = 0;
+    {
+        int dev = 0;
+        c->num_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            c->num_cu = 0;
+        if (c->num_cu <= 0) c->num_cu = 256;
+        for (auto &row : c->t2_slots)
+            for (int &v : row) v = 0;
+    }
     if (desc->solid) {
         e = hipMalloc(&c->links, sizeof(uint32_t) * c->nodes);
         if (e == hipSuccess) {

@@ -481,12 +481,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 
 // ------------------------------------------------------------------ two fused steps (temporal blocking)
 // Two time steps per launch on periodic lattices without solid nodes.  A block
-// owns a 32 x 8 tile of (x, y) columns and marches along a chunk of z planes.
+// owns a 32 x 12 tile of (x, y) columns and marches along a chunk of z planes.
 // For each plane it first runs step t -> t+1 on the tile plus a one-node halo
-// (34 x 10 nodes, pulling from HBM), keeping the results in LDS, and then step
+// (34 x 14 nodes, pulling from HBM), keeping the results in LDS, and then step
 // t+1 -> t+2 on the tile plane below, pulling those results from LDS and
 // writing to HBM.  The intermediate state never leaves the chip, so HBM moves
-// about 1.33 x 27 reads (the halo) and 27 writes per node for two updates
+// about 1.24 x 27 reads (the halo) and 27 writes per node for two updates
 // instead of 2 x (27 + 27).  Intermediate values are rounded to the storage
 // type exactly as a stored state would be, so the result is bitwise that of
 // two single steps.
@@ -495,11 +495,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 // from plane z and e_z = +1 from plane z-1 of the intermediate state.  Each
 // thread keeps its halo node's e_z = 0 group for one plane iteration and its
 // e_z = +1 group for two in registers and writes a group to LDS only in the
-// iteration that pulls it, so LDS holds just three groups of 9 x 340 values
-// (37 KB): three blocks (18 waves) fit on a CU, limited by the 87 VGPRs.
-constexpr int kT2X = 32, kT2Y = 8;
-constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 340 nodes
-constexpr int kT2Block = 384;                                               // >= kT2H, six wavefronts
+// iteration that pulls it, so LDS holds just three groups of 9 x 476 values
+// (51 KB per block).  The tile height was chosen by measurement (heights 6 to 16
+// on 512^3, 640x320x320 and 128^3 lattices; 12 was fastest on all three).
+constexpr int kT2X = 32, kT2Y = 12;
+constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 476 nodes
+constexpr int kT2Block = (kT2H + 63) / 64 * 64;                             // 512 threads, eight wavefronts
 
 struct T2Geom {
     uint32_t tiles_x, tiles_y, zchunk;
