@@ -159,7 +159,9 @@ const char *clbm_last_error(const clbm_ctx *ctx);
 
 /* Create a context for the lattice *desc (copied; the force buffer is
  * referenced, not copied, and must outlive its use).  stream: hipStream_t or
- * NULL.  Allocates small device scratch for reductions (< 1 MiB) and, when
+ * NULL.  Allocates device scratch for reductions (130 KiB; on D3Q27 cascaded
+ * lattices, whose adjoint keeps one row of partial sums per 256 nodes, 0.26
+ * bytes per node if that is more) and, when
  * desc->solid is given, a link table of 4 bytes per node built from the solid
  * mask and the walls by a kernel enqueued on `stream` (the mask must be ready
  * when that kernel runs; it is not referenced afterwards).  *out is set to NULL

@@ -27,7 +27,7 @@ struct clbm_ctx {
     hipStream_t stream;
     Geom geom;
     size_t nodes;
-    double *partials;  // [kMaxBlocks][kPartialStride]
+    double *partials;  // [partial_blocks + folded rows][kPartialStride]
     double *scal;      // [16] reduction results
     uint32_t *links;   // [N] link table (k_links) when the lattice has solid nodes, else NULL
     uint32_t options;  // CLBM_OPT_* flags
@@ -183,6 +183,16 @@ int dispatch_d3q27(clbm_ctx *c, F &&f)
 }
 
 unsigned node_blocks(const clbm_ctx *c) { return static_cast<unsigned>((c->nodes + kBlock - 1) / kBlock); }
+
+// Blocks whose partial sums the context's scratch holds: the grid-stride kernels
+// use at most kMaxBlocks; the adjoint and loss kernels (D3Q27 cascaded lattices
+// only) run one block per kBlock nodes.
+size_t partial_blocks(const clbm_ctx *c)
+{
+    const bool adjoint = c->d.lattice == CLBM_D3Q27 && c->d.collision == CLBM_CASCADED;
+    const size_t b = adjoint ? node_blocks(c) : 0;
+    return b > static_cast<size_t>(kMaxBlocks) ? b : static_cast<size_t>(kMaxBlocks);
+}
 unsigned stride_blocks(const clbm_ctx *c)
 {
     const unsigned b = node_blocks(c);
@@ -359,7 +369,8 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
             if (desc->wall_velocity[f][b] != 0.0) g.moving = 1;
         }
     std::snprintf(c->err, sizeof(c->err), "no error");
-    hipError_t e = hipMalloc(&c->partials, sizeof(double) * kMaxBlocks * kPartialStride);
+    const size_t pb = partial_blocks(c);
+    hipError_t e = hipMalloc(&c->partials, sizeof(double) * kPartialStride * (pb + (pb + kBlock - 1) / kBlock));
     if (e != hipSuccess) {
         rc = hip_fail(nullptr, e, "hipMalloc(partials)");
         delete c;
@@ -627,7 +638,7 @@ int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, 
         return fail(ctx, CLBM_EINVAL, "bad adjoint buffers");
     if (lam_next == lam_out) return fail(ctx, CLBM_EINVAL, "lam_next and lam_out must be distinct");
     if ((dJdF && !aligned(dJdF)) || (dJds && !aligned(dJds))) return fail(ctx, CLBM_EINVAL, "dJdF/dJds misaligned");
-    const unsigned nb = stride_blocks(ctx);
+    const unsigned nb = node_blocks(ctx);
     int rc = dispatch_d3q27(ctx, [&](auto v) {
         using Vt = decltype(v);
         using S = typename Vt::Store;
@@ -640,7 +651,18 @@ int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, 
         return check_launch(ctx, "adjoint kernel launch");
     });
     if (rc || !dJds) return rc;
-    hipLaunchKernelGGL(k_reduce, dim3(kAdjRates), dim3(kBlock), 0, ctx->stream, ctx->partials, static_cast<int>(nb),
+    const double *rows = ctx->partials;
+    unsigned nrows = nb;
+    if (nb > static_cast<unsigned>(kMaxBlocks)) {  // fold the long table first (fixed order)
+        double *folded = ctx->partials + partial_blocks(ctx) * kPartialStride;
+        nrows = (nb + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_fold<kAdjRates>, dim3(nrows), dim3(kBlock), 0, ctx->stream, ctx->partials,
+                           static_cast<int>(nb), folded);
+        rc = check_launch(ctx, "fold kernel launch");
+        if (rc) return rc;
+        rows = folded;
+    }
+    hipLaunchKernelGGL(k_reduce, dim3(kAdjRates), dim3(kBlock), 0, ctx->stream, rows, static_cast<int>(nrows),
                        kAdjRates, dJds + 2, 1);
     return check_launch(ctx, "reduce kernel launch");
 }

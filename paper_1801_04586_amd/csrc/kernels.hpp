@@ -641,6 +641,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ pa
     if (threadIdx.x == 0) out[c] = (accumulate ? out[c] : 0.0) + res[0];
 }
 
+// First stage for long partial tables: block b sums rows b*kBlock ... b*kBlock+kBlock-1
+// of partials[row][NC] (fixed order) into out[b][NC].
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_fold(const double *__restrict__ partials, int nrows,
+                                                 double *__restrict__ out)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = r < nrows ? partials[static_cast<size_t>(r) * NC + c] : 0.0;
+    block_reduce_store<NC>(acc, out + static_cast<size_t>(blockIdx.x) * NC);
+}
+
 // ------------------------------------------------------------------ macroscopic fields (Eq. (9))
 constexpr int kMomComp = 5;  // mass, momentum x/y/z, count of bad nodes
 
@@ -811,7 +824,9 @@ __global__ __launch_bounds__(kBlock) void k_init(S *__restrict__ dst, Geom g, co
 // conserved moments and have zero derivative.
 constexpr int kAdjRates = 8;
 
-// One adjoint step on one node per thread (grid-stride).  Recomputes the forward
+// One adjoint step on one node per thread (one thread per node, no grid-stride
+// loop: a loop around this body keeps loop-invariant values in VGPRs and halves
+// the occupancy).  Recomputes the forward
 // moments from the state at t, gathers lambda(t+1) along +e (the transpose of
 // the pull), applies the transposed per-node Jacobian and writes lambda(t).
 //
@@ -835,7 +850,8 @@ __device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const
     using R = typename Traits<S>::R;
     constexpr R cs2 = R(1.0 / 3.0), cs4 = R(1.0 / 9.0);
     double gs[kAdjRates] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.N; n += gridDim.x * kBlock) {
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n < g.N) {
         // A solid node reads no state or adjoint: with zero inputs every output below is
         // exactly zero (lambda = 0, no force or rate contribution), and its stores keep
         // the wavefront's cache lines whole.
