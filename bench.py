@@ -391,8 +391,13 @@ def main():
         pb = 2 * 27 * 4 * fluid + pn  # populations of fluid nodes + the solid mask
         variants["porous_640x320x320_f32"] = {
             "mlups": round(pn / (ms * 1e-3) / 1e6, 1), "mflups_fluid": round(fluid / (ms * 1e-3) / 1e6, 1),
-            "kernel_ms": round(ms, 4), "bytes_per_node": round(pb / pn, 2),
+            "ms_per_step": round(ms, 4), "launch": "two fused steps" if lp.uses_fused_pairs else "one step",
+            "bytes_per_node": round(pb / pn, 2),
             "frac": round(pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "solid_fraction": round(1 - fluid / pn, 4)}
+        if lp.uses_fused_pairs:
+            lp.set_fused_steps(False)
+            ms1 = time_steps(torch, lp, 10)
+            variants["porous_640x320x320_f32"]["single_step_mlups"] = round(pn / (ms1 * 1e-3) / 1e6, 1)
         log(f"[bench] porous: {variants['porous_640x320x320_f32']}")
         lp.close()
         del lp

@@ -197,10 +197,11 @@ int clbm_step(clbm_ctx *ctx, const void *src, void *dst);
 
 /* nsteps steps from the state in a, using a and b as the two buffers; the
  * buffer that holds the final state is returned in *result (host, may be
- * NULL).  On periodic D3Q27 lattices without solid nodes, with FP32 storage
- * and the cascaded collision, pairs of steps run as one fused launch that
- * keeps the intermediate state on chip (bitwise the same result as two
- * clbm_step calls); otherwise every step is one clbm_step.  nsteps >= 0. */
+ * NULL).  On D3Q27 lattices with FP32 storage and the cascaded collision
+ * that are periodic or have solid nodes (walls allowed with solids), and have
+ * no moving walls, pairs of steps run as one fused launch that keeps the
+ * intermediate state on chip (bitwise the same result as two clbm_step calls);
+ * otherwise every step is one clbm_step.  nsteps >= 0. */
 int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result);
 
 /* Option flags (clbm_set_options). */

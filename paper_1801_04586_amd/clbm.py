@@ -368,7 +368,8 @@ class Lattice:
     def uses_fused_pairs(self) -> bool:
         """Whether step(n) runs pairs of steps as one fused launch (the rule of clbm_run)."""
         return (getattr(self, "_fused", True) and self.lattice == "d3q27" and self.storage == "f32"
-                and self.collision == "cascaded" and self.walls == (0, 0, 0) and self.solid is None)
+                and self.collision == "cascaded" and not np.any(self.wall_velocity)
+                and (self.solid is not None or tuple(self.walls) == (0, 0, 0)))
 
     def set_rates(self, rates):
         self.rates = np.asarray(rates, dtype=np.float64)

@@ -32,7 +32,7 @@ struct clbm_ctx {
     uint32_t *links;   // [N] link table (k_links) when the lattice has solid nodes, else NULL
     uint32_t options;  // CLBM_OPT_* flags
     int num_cu;        // compute units of the device
-    int t2_slots[2][2];  // resident blocks of the fused kernel on the device, by (force field, collision); 0 = unknown
+    int t2_slots[2][2][2];  // resident blocks of the fused kernel, by (links, force field, collision); 0 = unknown
     char err[512];
 };
 
@@ -239,16 +239,19 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
     });
 }
 
-// Two fused steps per launch apply to periodic D3Q27 lattices without solids with
-// FP32 storage and the cascaded collision.  FP64 does not fit the LDS groups at
+// Two fused steps per launch apply to D3Q27 lattices with FP32 storage and the
+// cascaded collision, either periodic or with a link table (solid nodes, with or
+// without walls), and without moving walls.  FP64 does not fit the LDS groups at
 // this tile size; for 16-bit storage (half the bytes of FP32) the single-step
 // kernel is faster, the fused kernel's cost per step being set by its arithmetic
 // and barriers rather than by memory; and the MRT's larger register footprint
 // leaves the fused kernel two blocks per CU, slower than single steps.
 bool fused_pairs(const clbm_ctx *c)
 {
-    return !(c->options & CLBM_OPT_SINGLE_STEP) && c->d.lattice == CLBM_D3Q27 && c->d.storage == CLBM_F32 &&
-           c->d.collision == CLBM_CASCADED && !c->links && !c->d.wall[0] && !c->d.wall[1] && !c->d.wall[2];
+    if ((c->options & CLBM_OPT_SINGLE_STEP) || c->d.lattice != CLBM_D3Q27 || c->d.storage != CLBM_F32 ||
+        c->d.collision != CLBM_CASCADED || c->geom.moving)
+        return false;
+    return c->links || (!c->d.wall[0] && !c->d.wall[1] && !c->d.wall[2]);
 }
 
 // A block of the fused kernel runs through a whole z chunk, so a launch whose last
@@ -281,17 +284,19 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
     tg.tiles_y = (c->geom.ny + kT2Y - 1) / kT2Y;
     const uint32_t tiles = tg.tiles_x * tg.tiles_y;
     const int coll = collision_of(c);
-    auto go = [&](auto tag, auto field_tag) {
+    auto go = [&](auto tag, auto field_tag, auto solid_tag) {
         using S = decltype(tag);
         using R = typename Traits<S>::R;
         constexpr bool FIELD = decltype(field_tag)::value;
+        constexpr bool SOLID = decltype(solid_tag)::value;
         auto launch = [&](auto cc) {
             constexpr int C = decltype(cc)::value;
-            int &slots = c->t2_slots[FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0];
+            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0];
             if (slots == 0) {
                 int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C>, kT2Block, 0) !=
-                        hipSuccess || per_cu < 1)
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID>, kT2Block,
+                                                                 0) != hipSuccess ||
+                    per_cu < 1)
                     per_cu = 1;
                 slots = per_cu * c->num_cu;
             }
@@ -299,15 +304,19 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
             tg.zchunk = (c->geom.nz + nchunks_req - 1) / nchunks_req;
             const uint32_t nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
             const unsigned blocks = tiles * nchunks;
-            hipLaunchKernelGGL((k_step2<S, FIELD, C>), dim3(blocks), dim3(kT2Block), 0, c->stream,
-                               static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg,
+            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID>), dim3(blocks), dim3(kT2Block), 0, c->stream,
+                               static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg, c->links,
                                static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
             return check_launch(c, "fused two-step kernel launch");
         };
         if (coll == kCascadedHigh1) return launch(std::integral_constant<int, kCascadedHigh1>{});
         return launch(std::integral_constant<int, kCascaded>{});
     };
-    return c->d.force != nullptr ? go(float{}, std::true_type{}) : go(float{}, std::false_type{});
+    if (c->links)
+        return c->d.force != nullptr ? go(float{}, std::true_type{}, std::true_type{})
+                                     : go(float{}, std::false_type{}, std::true_type{});
+    return c->d.force != nullptr ? go(float{}, std::true_type{}, std::false_type{})
+                                 : go(float{}, std::false_type{}, std::false_type{});
 }
 
 }  // namespace
@@ -392,8 +401,9 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
             hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             c->num_cu = 0;
         if (c->num_cu <= 0) c->num_cu = 256;
-        for (auto &row : c->t2_slots)
-            for (int &v : row) v = 0;
+        for (auto &plane : c->t2_slots)
+            for (auto &row : plane)
+                for (int &v : row) v = 0;
     }
     if (desc->solid) {
         e = hipMalloc(&c->links, sizeof(uint32_t) * c->nodes);

@@ -480,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 }
 
 // ------------------------------------------------------------------ two fused steps (temporal blocking)
-// Two time steps per launch on periodic lattices without solid nodes.  A block
+// Two time steps per launch on FP32 lattices without moving walls.  A block
 // owns a 32 x 12 tile of (x, y) columns and marches along a chunk of z planes.
 // For each plane it first runs step t -> t+1 on the tile plus a one-node halo
 // (34 x 14 nodes, pulling from HBM), keeping the results in LDS, and then step
@@ -498,6 +498,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 // iteration that pulls it, so LDS holds just three groups of 9 x 476 values
 // (51 KB per block).  The tile height was chosen by measurement (heights 6 to 16
 // on 512^3, 640x320x320 and 128^3 lattices; 12 was fastest on all three).
+//
+// With solid nodes or walls (SOLID: the link table holds every node's open
+// links) the bounce-back of Eq. (8) in step t+2 takes the node's own opposite
+// population from step t+1.  The tile's nodes are then stepped a second time by
+// the threads of their own halo positions, which hold the node's e_z = +1 group
+// and link word in registers; the e_z = 0 group of plane z is in LDS, and the
+// e_z = -1 groups alternate between two LDS slots by plane parity so that plane
+// z's stays readable while plane z+1's is written (68.5 KB per block).
 constexpr int kT2X = 32, kT2Y = 12;
 constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 476 nodes
 constexpr int kT2Block = (kT2H + 63) / 64 * 64;                             // 512 threads, eight wavefronts
@@ -513,15 +521,18 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
 }
 
 // (the waves-per-EU bound keeps the register budget at or below 128)
-template <typename S, bool FIELD, int COLL>
+template <typename S, bool FIELD, int COLL, bool SOLID>
 __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) void k_step2(
-    const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const typename Traits<S>::R *__restrict__ field,
-    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
+    const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const uint32_t *__restrict__ links,
+    const typename Traits<S>::R *__restrict__ field, Forcing<typename Traits<S>::R> fo,
+    Rates<typename Traits<S>::R> rt)
 {
     using R = typename Traits<S>::R;
     static_assert(std::is_same<R, float>::value, "the LDS ring holds FP32 values");
-    // [0]: e_z = -1 group of plane z+1, [1]: e_z = 0 group of plane z, [2]: e_z = +1 group of plane z-1
-    __shared__ float ring[3][9][kT2H];
+    // [0]: e_z = -1 group of plane z+1, [1]: e_z = 0 group of plane z, [2]: e_z = +1 group of plane z-1;
+    // with SOLID, [0] and [3] hold the e_z = -1 groups of even and odd planes
+    __shared__ float ring[SOLID ? 4 : 3][9][kT2H];
+    auto zm = [](int p) { return SOLID && (p & 1) ? 3 : 0; };
 
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t tx = b % tg.tiles_x, rest = b / tg.tiles_x;
@@ -531,8 +542,32 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     const int z1 = min(z0 + static_cast<int>(tg.zchunk), static_cast<int>(g.nz));
     const int tid = threadIdx.x;
 
+    // Halo position (hx, hy) of this thread in step t+1 and its LDS index hs = hy * kT2HX + hx.
+    // Without solids: row-major (hs = tid); step t+2 of tile node (cx, cy) runs on thread
+    // cy * kT2X + cx.  With solids, step t+2 of a tile node must run on the thread that stepped
+    // it in t+1 (its registers hold the node's own values), so threads 0 ... 383 take the tile
+    // nodes row by row and 384 ... 475 the halo ring: rows hy = 0 and 13, then columns hx = 0 and 33.
+    int hx, hy;
+    if constexpr (SOLID) {
+        constexpr int kCore = kT2X * kT2Y, kRows = 2 * kT2X;
+        if (tid < kCore) {
+            hx = 1 + tid % kT2X;
+            hy = 1 + tid / kT2X;
+        } else if (tid < kCore + kRows) {
+            const int r = tid - kCore;
+            hx = 1 + r % kT2X;
+            hy = r < kT2X ? 0 : kT2HY - 1;
+        } else {
+            const int r = tid - kCore - kRows;
+            hx = r < kT2HY ? 0 : kT2HX - 1;
+            hy = r % kT2HY;
+        }
+    } else {
+        hx = tid % kT2HX;
+        hy = tid / kT2HX;
+    }
+    const int hs = hy * kT2HX + hx;
     const bool ha = tid < kT2H;
-    const int hx = tid % kT2HX, hy = tid / kT2HX;
     const uint32_t gx = wrap_coord(x0 - 1 + hx, g.nx), gy = wrap_coord(y0 - 1 + hy, g.ny);
     const int cx = tid % kT2X, cy = tid / kT2X;
     const bool ca = tid < kT2X * kT2Y && x0 + cx < static_cast<int>(g.nx) && y0 + cy < static_cast<int>(g.ny);
@@ -540,6 +575,7 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     // groups of the halo node's intermediate values kept in registers until the plane that pulls
     // them: e_z = 0 of plane p, e_z = +1 of planes p - 1 and p (p: the last plane computed)
     float keep0[9], keep2a[9], keep2b[9];
+    uint32_t lm_a = 0, lm_b = 0;  // SOLID: the halo node's link words in planes p - 1 and p
 
     auto first_step = [&](int p) {
         if (!ha) return;
@@ -549,18 +585,29 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         neighbours_xyz(g, gx, gy, pz, nb);
         constexpr uint32_t es = sizeof(S);
         R v[27];
-        sfor<0, 27>([&](auto TT) {
-            constexpr int t = decltype(TT)::value;
-            uint32_t off;
-            link_open<t, false, false>(nb, 0u, off);
-            v[t] = to_real(load_at(src + static_cast<size_t>(pop_of_slot(t)) * g.P, off * es));
-        });
+        if constexpr (SOLID) {
+            const uint32_t lm = links[n];
+            lm_a = lm_b;
+            lm_b = lm;
+            if (lm != 0u)
+                gather<S, true, true, false>(src, g, n, nb, lm, v);
+            else
+                sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });  // solid: the rest state, as step_node
+        } else {
+            sfor<0, 27>([&](auto TT) {
+                constexpr int t = decltype(TT)::value;
+                uint32_t off;
+                link_open<t, false, false>(nb, 0u, off);
+                v[t] = to_real(load_at(src + static_cast<size_t>(pop_of_slot(t)) * g.P, off * es));
+            });
+        }
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
         node_update<COLL>(v, Fx, Fy, Fz, rt);
+        const int r0 = zm(p);
         sfor<0, 9>([&](auto J) {
             constexpr int j = decltype(J)::value;  // j = 3 a + b; slot 3 j + c with c = e_z + 1
-            ring[0][j][tid] = static_cast<float>(to_store<S>(v[3 * j + 0]));  // the value a stored state would hold
+            ring[r0][j][hs] = static_cast<float>(to_store<S>(v[3 * j + 0]));  // the value a stored state would hold
             keep2a[j] = keep2b[j];
             keep0[j] = static_cast<float>(to_store<S>(v[3 * j + 1]));
             keep2b[j] = static_cast<float>(to_store<S>(v[3 * j + 2]));
@@ -570,14 +617,47 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     auto second_step = [&](int z) {
         if (!ca) return;
         const uint32_t zz = wrap_coord(z, g.nz);
-        const uint32_t n = static_cast<uint32_t>(x0 + cx) + g.nx * (static_cast<uint32_t>(y0 + cy) + g.ny * zz);
+        // with solids this thread stepped the same node in t+1: (gx, gy) and hs are the tile node's
+        const uint32_t n = SOLID ? gx + g.nx * (gy + g.ny * zz)
+                                 : static_cast<uint32_t>(x0 + cx) + g.nx * (static_cast<uint32_t>(y0 + cy) + g.ny * zz);
+        const int hn = SOLID ? hs : (cy + 1) * kT2HX + (cx + 1);  // LDS index of the tile node
         R v[27];
-        sfor<0, 27>([&](auto TT) {
+        // slot t pulls from the halo position of x - e; index into the ring viewed as one array
+        const float *rf = &ring[0][0][0];
+        const int rz = zm(z + 1);
+        auto pulled_at = [&](auto TT) -> int {
             constexpr int t = decltype(TT)::value;
             constexpr int a = sa(t), bb = sb(t), c = sc(t), j = 3 * a + bb;
-            const int h = (cy + 2 - bb) * kT2HX + (cx + 2 - a);
-            v[t] = ring[c][j][h];
-        });
+            return ((c == 0 ? rz : c) * 9 + j) * kT2H + hn + (1 - bb) * kT2HX + (1 - a);
+        };
+        if constexpr (SOLID) {
+            const uint32_t lm = lm_a;
+            if (lm == 0u) {
+                sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });
+            } else if (__all(lm == all_links<27>())) {
+                sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = rf[pulled_at(TT)]; });
+            } else {
+                // a blocked link returns the node's own opposite population of step t+1 (Eq. (8))
+                const int ro = zm(z);
+                sfor<0, 27>([&](auto TT) {
+                    constexpr int t = decltype(TT)::value;
+                    constexpr int jo = 8 - (3 * sa(t) + sb(t)), co = 2 - sc(t);
+                    const float nbv = rf[pulled_at(TT)];
+                    if constexpr (t == 13) {
+                        v[t] = nbv;
+                    } else {
+                        float own;
+                        if constexpr (co == 2)
+                            own = keep2a[jo];
+                        else
+                            own = rf[((co == 0 ? ro : 1) * 9 + jo) * kT2H + hn];
+                        v[t] = (lm >> t) & 1u ? nbv : own;
+                    }
+                });
+            }
+        } else {
+            sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = rf[pulled_at(TT)]; });
+        }
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
         node_update<COLL>(v, Fx, Fy, Fz, rt);
@@ -596,10 +676,10 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         if (ha)
             sfor<0, 9>([&](auto J) {
                 constexpr int j = decltype(J)::value;
-                ring[1][j][tid] = keep0[j];   // e_z = 0 of plane z
-                ring[2][j][tid] = keep2a[j];  // e_z = +1 of plane z - 1
+                ring[1][j][hs] = keep0[j];   // e_z = 0 of plane z
+                ring[2][j][hs] = keep2a[j];  // e_z = +1 of plane z - 1
             });
-        first_step(z + 1);  // ring[0] <- e_z = -1 of plane z + 1
+        first_step(z + 1);  // ring[zm(z + 1)] <- e_z = -1 of plane z + 1
         __syncthreads();    // the three groups of second_step(z) are in the ring
         second_step(z);
     }

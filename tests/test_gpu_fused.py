@@ -1,7 +1,8 @@
-"""Fused two-step launches (clbm_run on FP32 periodic lattices without solids)
-are bitwise identical to single steps, across ragged tiles, thin lattices, odd
-step counts, both collision paths and with or without a force field; and they
-match the oracle."""
+"""Fused two-step launches (clbm_run on FP32 cascaded D3Q27 lattices, periodic
+or with solid nodes and walls) are bitwise identical to single steps, across
+ragged tiles, thin lattices, odd step counts, both collision paths, with or
+without a force field, every wall combination, random solids and packed
+spheres; and they match the oracle."""
 from __future__ import annotations
 
 import numpy as np
@@ -58,17 +59,94 @@ def test_fused_pairs_without_force_field(rates):
     assert torch.equal(a, b)
 
 
-def test_fused_pairs_apply_to_fp32_periodic_lattices_only():
+def test_fused_pairs_apply_to_fp32_lattices_periodic_or_with_solids():
     from paper_1801_04586_amd import Lattice
 
     dims = (8, 8, 8)
-    cases = [("f32", (0, 0, 0), None, True), ("f64", (0, 0, 0), None, False), ("f16", (0, 0, 0), None, False),
-             ("bf16", (0, 0, 0), None, False), ("f32", (0, 1, 0), None, False),
-             ("f32", (0, 0, 0), workloads.random_solids(dims, 0.1, 9), False)]
-    for storage, walls, solid, fused in cases:
-        lat = Lattice(dims, walls, storage, RATES, solid=solid)
-        assert lat.uses_fused_pairs == fused, (storage, walls)
+    sol = workloads.random_solids(dims, 0.1, 9)
+    cases = [("f32", (0, 0, 0), None, None, True), ("f64", (0, 0, 0), None, None, False),
+             ("f16", (0, 0, 0), None, None, False), ("bf16", (0, 0, 0), None, None, False),
+             ("f32", (0, 1, 0), None, None, False), ("f32", (0, 0, 0), sol, None, True),
+             ("f32", (1, 1, 1), sol, None, True), ("f64", (0, 1, 0), sol, None, False),
+             ("f32", (0, 1, 0), sol, {(1, 1): (0.01, 0.0, 0.0)}, False)]
+    for storage, walls, solid, wv, fused in cases:
+        lat = Lattice(dims, walls, storage, RATES, solid=solid, wall_velocity=wv)
+        assert lat.uses_fused_pairs == fused, (storage, walls, solid is not None, wv)
         lat.close()
+
+
+def _run_solid(dims, walls, solid, steps, fused, f0, field, rates=RATES):
+    from paper_1801_04586_amd import Lattice
+
+    lat = Lattice(dims, walls, "f32", rates, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid)
+    assert lat.uses_fused_pairs
+    lat.set_fused_steps(fused)
+    lat.set_populations(torch.from_numpy(f0))
+    lat.step(steps)
+    out = lat.state.clone()
+    pops = lat.populations().cpu().numpy()
+    lat.close()
+    return out, pops
+
+
+def _start_walls(dims, walls, seed):
+    g = oracle.Geometry(dims, walls)
+    rho0, u0 = workloads.random_state_fields(dims, seed, du=0.05, drho=0.02)
+    return g, oracle.init(g, rho0, u0) + workloads.random_populations_perturbation(dims, seed + 1, 1e-3)
+
+
+@pytest.mark.parametrize("dims,walls", [((67, 19, 13), (0, 1, 1)), ((32, 24, 16), (0, 0, 0)), ((33, 9, 40), (1, 1, 1)),
+                                        ((5, 7, 2), (1, 0, 1)), ((96, 17, 1), (0, 1, 0)), ((1, 13, 9), (0, 1, 1)),
+                                        ((40, 12, 3), (0, 0, 1))])
+@pytest.mark.parametrize("rates", [RATES, RATES_H1], ids=["general", "high1"])
+def test_fused_pairs_with_solids_are_bitwise_single_steps(dims, walls, rates):
+    g, f0 = _start_walls(dims, walls, 21)
+    field = workloads.gaussian_force(dims, 1e-4, 22)
+    solid = workloads.random_solids(dims, 0.2, 23)
+    for steps in (2, 5):
+        a, _ = _run_solid(dims, walls, solid, steps, True, f0, field, rates)
+        b, _ = _run_solid(dims, walls, solid, steps, False, f0, field, rates)
+        assert torch.equal(a, b), (dims, walls, steps)
+
+
+def test_fused_pairs_with_packed_spheres_and_without_force_field():
+    dims, walls = (70, 40, 36), (0, 1, 1)
+    g, f0 = _start_walls(dims, walls, 31)
+    solid, _, _ = workloads.porous_spheres(dims, walls, 3.0, 6.0, 0.2, 32)
+    a, _ = _run_solid(dims, walls, solid, 6, True, f0, None, RATES_H1)
+    b, _ = _run_solid(dims, walls, solid, 6, False, f0, None, RATES_H1)
+    assert torch.equal(a, b)
+
+
+def test_fused_pairs_with_walls_and_an_all_fluid_mask():
+    """A solid mask without solid nodes still gives the lattice a link table: walls alone then take the
+    fused path's bounce-back."""
+    dims, walls = (34, 26, 11), (1, 1, 0)
+    g, f0 = _start_walls(dims, walls, 41)
+    solid = np.zeros((11, 26, 34), np.uint8)
+    a, _ = _run_solid(dims, walls, solid, 4, True, f0, None)
+    b, _ = _run_solid(dims, walls, solid, 4, False, f0, None)
+    assert torch.equal(a, b)
+
+
+def test_fused_run_with_solids_matches_oracle():
+    dims, walls = (37, 14, 9), (0, 1, 0)
+    g, f0 = _start_walls(dims, walls, 51)
+    field = workloads.gaussian_force(dims, 1e-4, 52)
+    solid = workloads.random_solids(dims, 0.15, 53)
+    from paper_1801_04586_amd import Lattice
+
+    lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid)
+    assert lat.uses_fused_pairs
+    lat.set_populations(torch.from_numpy(f0))
+    start = lat.populations().cpu().numpy()
+    lat.step(4)
+    got = lat.populations().cpu().numpy()
+    ref = oracle.run(g, start, RATES, 4, force=(1e-5, -3e-6, 2e-6), force_field=lat.force_field.double().cpu().numpy(),
+                     solid=solid)
+    fl = solid == 0
+    assert np.max(np.abs(got[:, fl] - ref[:, fl])) < 1e-7
+    lat.close()
 
 
 def test_fused_run_matches_oracle():
