@@ -229,7 +229,7 @@ def main():
         # the same lattice with one step per launch, for comparison
         lat.set_fused_steps(False)
         ms1 = time_steps(torch, lat, 10)
-        lat.set_fused_steps(True)
+        lat.set_fused_steps(None)
         result["single_step_kernel"] = {
             "mlups": round(nodes / (ms1 * 1e-3) / 1e6, 1), "kernel_ms": round(ms1, 4),
             "frac": round(bpn * nodes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -276,7 +276,7 @@ def main():
             if lv.uses_fused_pairs:
                 lv.set_fused_steps(False)
                 ms1 = time_steps(torch, lv, 10)
-                lv.set_fused_steps(True)
+                lv.set_fused_steps(None)
                 variants[f"kolmogorov_{L}_{storage}"]["single_step_mlups"] = round(nodes / (ms1 * 1e-3) / 1e6, 1)
             log(f"[bench] {storage}: {ms:.3f} ms/step, {variants[f'kolmogorov_{L}_{storage}']}")
             lv.close()
@@ -287,12 +287,10 @@ def main():
         lv.init(None, u0_dev)
         lv.step(4)
         ms = time_steps(torch, lv, 10)
-        lv.set_fused_steps(False)
-        ms1 = time_steps(torch, lv, 10)
         b = bytes_per_node("f32", True, False)
         variants[f"kolmogorov_{L}_mrt_f32"] = {
-            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4), "launch": "two fused steps",
-            "single_step_mlups": round(nodes / (ms1 * 1e-3) / 1e6, 1), "bytes_per_node": b,
+            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "launch": "two fused steps" if lv.uses_fused_pairs else "one step", "bytes_per_node": b,
             "frac": round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"[bench] MRT f32: {variants[f'kolmogorov_{L}_mrt_f32']}")
         lv.close()
@@ -331,8 +329,13 @@ def main():
             ms = time_steps(torch, lv, 10)
             b = bytes_per_node("f32", False, False)
             variants[f"cavity_256_{coll}_f32"] = {
-                "mlups": round(256 ** 3 / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4), "bytes_per_node": b,
+                "mlups": round(256 ** 3 / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                "launch": "two fused steps" if lv.uses_fused_pairs else "one step", "bytes_per_node": b,
                 "frac": round(b * 256 ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            if lv.uses_fused_pairs:
+                lv.set_fused_steps(False)
+                ms1 = time_steps(torch, lv, 10)
+                variants[f"cavity_256_{coll}_f32"]["single_step_mlups"] = round(256 ** 3 / (ms1 * 1e-3) / 1e6, 1)
             log(f"[bench] cavity {coll}: {variants[f'cavity_256_{coll}_f32']}")
             lv.close()
             del lv

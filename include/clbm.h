@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 4
+#define CLBM_ABI_VERSION 5
 
 /* Velocity sets: D3Q27 (Eq. (1), moment set Eq. (12)) and D3Q19 (Appendix A,
  * Eq. (A1)-(A6): velocities without the eight corners, moments of Eq. (A2),
@@ -162,10 +162,11 @@ const char *clbm_last_error(const clbm_ctx *ctx);
  * NULL.  Allocates device scratch for reductions (130 KiB; on D3Q27 cascaded
  * lattices, whose adjoint keeps one row of partial sums per 256 nodes, 0.26
  * bytes per node if that is more) and, when
- * desc->solid is given, a link table of 4 bytes per node built from the solid
- * mask and the walls by a kernel enqueued on `stream` (the mask must be ready
- * when that kernel runs; it is not referenced afterwards).  *out is set to NULL
- * on error. */
+ * desc->solid is given or the lattice has walls and takes fused step pairs
+ * (see clbm_run), a link table of 4 bytes per node built from the solid mask
+ * and the walls by a kernel enqueued on `stream` (the mask must be ready when
+ * that kernel runs; it is not referenced afterwards).  *out is set to NULL on
+ * error. */
 int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream);
 
 /* Release the context and its scratch (synchronises its stream). NULL is a no-op. */
@@ -198,17 +199,25 @@ int clbm_step(clbm_ctx *ctx, const void *src, void *dst);
 /* nsteps steps from the state in a, using a and b as the two buffers; the
  * buffer that holds the final state is returned in *result (host, may be
  * NULL).  On D3Q27 lattices with FP32 storage and the cascaded collision
- * that are periodic or have solid nodes (walls allowed with solids), and have
- * no moving walls, pairs of steps run as one fused launch that keeps the
- * intermediate state on chip (bitwise the same result as two clbm_step calls);
- * otherwise every step is one clbm_step.  nsteps >= 0. */
+ * (any walls, moving or not, and solid nodes), pairs of steps run as one fused
+ * launch that keeps the intermediate state on chip (bitwise the same result as
+ * two clbm_step calls) when the lattice fills the device: its 32 x 12 (x, y)
+ * tile columns times z chunks of 8 planes give at least two blocks per compute
+ * unit (CLBM_OPT_* flags override this); otherwise every step is one
+ * clbm_step.  nsteps >= 0. */
 int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result);
 
 /* Option flags (clbm_set_options). */
 #define CLBM_OPT_SINGLE_STEP 1u /* clbm_run launches one step at a time */
+#define CLBM_OPT_FUSED_PAIRS 2u /* fused pairs on every lattice that allows them, whatever its size */
 
-/* Set the CLBM_OPT_* flags of a context (default 0). */
+/* Set the CLBM_OPT_* flags of a context (default 0: fused pairs chosen by
+ * lattice size).  Setting both flags is CLBM_EINVAL. */
 int clbm_set_options(clbm_ctx *ctx, uint32_t options);
+
+/* 1 when clbm_run on this context runs pairs of steps as fused launches, 0 when
+ * it runs single steps, CLBM_EINVAL for a NULL ctx. */
+int clbm_fused_pairs(const clbm_ctx *ctx);
 
 /* Copy a whole state buffer, Q x P elements (checkpoints).  src and dst
  * distinct. */

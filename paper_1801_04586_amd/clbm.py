@@ -23,7 +23,7 @@ STORAGE_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float1
 # arithmetic / adjoint / force-field type per storage
 REAL_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float32, "bf16": torch.float32}
 RATE_NAMES = ("s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6")
-ABI_VERSION = 4  # CLBM_ABI_VERSION of include/clbm.h
+ABI_VERSION = 5  # CLBM_ABI_VERSION of include/clbm.h
 CLBM_D3Q27, CLBM_D3Q19 = 0, 1
 LATTICE = {"d3q27": CLBM_D3Q27, "d3q19": CLBM_D3Q19}
 LATTICE_Q = {"d3q27": 27, "d3q19": 19}
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "clbm_step": ([vp, vp, vp], ctypes.c_int),
         "clbm_run": ([vp, vp, vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
         "clbm_set_options": ([vp, ctypes.c_uint32], ctypes.c_int),
+        "clbm_fused_pairs": ([vp], ctypes.c_int),
         "clbm_copy": ([vp, vp, vp], ctypes.c_int),
         "clbm_moments": ([vp, vp, vp, vp, dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "clbm_get_populations": ([vp, vp, vp], ctypes.c_int),
@@ -186,6 +187,12 @@ class Context:
 
     def set_options(self, options: int):
         self._call("clbm_set_options", ctypes.c_uint32(int(options)))
+
+    def fused_pairs(self) -> bool:
+        r = self.lib.clbm_fused_pairs(self._h)
+        if r < 0:
+            raise ClbmError("clbm_fused_pairs", r, self.lib.clbm_last_error(self._h).decode())
+        return r == 1
 
     def copy(self, src, dst):
         self._call("clbm_copy", self._state(src), self._state(dst))
@@ -359,17 +366,15 @@ class Lattice:
         self.t += n
         return self
 
-    def set_fused_steps(self, enabled: bool):
-        """Allow (default) or forbid the fused two-step launches of clbm_run."""
-        self.ctx.set_options(0 if enabled else 1)
-        self._fused = bool(enabled)
+    def set_fused_steps(self, enabled: Optional[bool]):
+        """Fused two-step launches of clbm_run: None = chosen by lattice size (default),
+        True = whenever the lattice allows them, False = never."""
+        self.ctx.set_options(0 if enabled is None else (2 if enabled else 1))
 
     @property
     def uses_fused_pairs(self) -> bool:
-        """Whether step(n) runs pairs of steps as one fused launch (the rule of clbm_run)."""
-        return (getattr(self, "_fused", True) and self.lattice == "d3q27" and self.storage == "f32"
-                and self.collision == "cascaded" and not np.any(self.wall_velocity)
-                and (self.solid is not None or tuple(self.walls) == (0, 0, 0)))
+        """Whether step(n) runs pairs of steps as one fused launch (asks clbm_fused_pairs)."""
+        return self.ctx.fused_pairs()
 
     def set_rates(self, rates):
         self.rates = np.asarray(rates, dtype=np.float64)

@@ -240,18 +240,29 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
 }
 
 // Two fused steps per launch apply to D3Q27 lattices with FP32 storage and the
-// cascaded collision, either periodic or with a link table (solid nodes, with or
-// without walls), and without moving walls.  FP64 does not fit the LDS groups at
+// cascaded collision, either periodic or with a link table (solid nodes or walls,
+// moving or not).  FP64 does not fit the LDS groups at
 // this tile size; for 16-bit storage (half the bytes of FP32) the single-step
 // kernel is faster, the fused kernel's cost per step being set by its arithmetic
 // and barriers rather than by memory; and the MRT's larger register footprint
 // leaves the fused kernel two blocks per CU, slower than single steps.
+bool fused_kind(const clbm_desc &d)
+{
+    return d.lattice == CLBM_D3Q27 && d.storage == CLBM_F32 && d.collision == CLBM_CASCADED;
+}
+
+// A lattice too small to give the fused kernel two blocks per compute unit (tile
+// columns x z chunks of at least 8 planes) runs single steps by default, whose
+// 256-node blocks fill the device (64^3: 96 fused blocks, 25.9 us per step
+// against 13.8 us for single steps).
 bool fused_pairs(const clbm_ctx *c)
 {
-    if ((c->options & CLBM_OPT_SINGLE_STEP) || c->d.lattice != CLBM_D3Q27 || c->d.storage != CLBM_F32 ||
-        c->d.collision != CLBM_CASCADED || c->geom.moving)
-        return false;
-    return c->links || (!c->d.wall[0] && !c->d.wall[1] && !c->d.wall[2]);
+    if ((c->options & CLBM_OPT_SINGLE_STEP) || !fused_kind(c->d)) return false;
+    if (!c->links && (c->d.wall[0] || c->d.wall[1] || c->d.wall[2])) return false;
+    if (c->options & CLBM_OPT_FUSED_PAIRS) return true;
+    const uint64_t tiles = static_cast<uint64_t>((c->geom.nx + kT2X - 1) / kT2X) * ((c->geom.ny + kT2Y - 1) / kT2Y);
+    const uint64_t chunks = c->geom.nz / 8 > 1 ? c->geom.nz / 8 : 1;
+    return tiles * chunks >= 2 * static_cast<uint64_t>(c->num_cu);
 }
 
 // A block of the fused kernel runs through a whole z chunk, so a launch whose last
@@ -375,7 +386,7 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
     for (int f = 0; f < 6; ++f)
         for (int b = 0; b < 3; ++b) {
             g.wu[f][b] = desc->wall_velocity[f][b];
-            if (desc->wall_velocity[f][b] != 0.0) g.moving = 1;
+            if (desc->wall_velocity[f][b] != 0.0) g.moving |= 1 << f;
         }
     std::snprintf(c->err, sizeof(c->err), "no error");
     const size_t pb = partial_blocks(c);
@@ -405,7 +416,9 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
             for (auto &row : plane)
                 for (int &v : row) v = 0;
     }
-    if (desc->solid) {
+    // the link table: for solid nodes, and for walls on lattices that take the fused kernel
+    const bool walls = desc->wall[0] || desc->wall[1] || desc->wall[2];
+    if (desc->solid || (walls && fused_kind(*desc))) {
         e = hipMalloc(&c->links, sizeof(uint32_t) * c->nodes);
         if (e == hipSuccess) {
             if (desc->lattice == CLBM_D3Q19)
@@ -533,9 +546,18 @@ int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result)
 int clbm_set_options(clbm_ctx *ctx, uint32_t options)
 {
     if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
-    if (options & ~static_cast<uint32_t>(CLBM_OPT_SINGLE_STEP)) return fail(ctx, CLBM_EINVAL, "unknown option bits");
+    if (options & ~static_cast<uint32_t>(CLBM_OPT_SINGLE_STEP | CLBM_OPT_FUSED_PAIRS))
+        return fail(ctx, CLBM_EINVAL, "unknown option bits");
+    if ((options & CLBM_OPT_SINGLE_STEP) && (options & CLBM_OPT_FUSED_PAIRS))
+        return fail(ctx, CLBM_EINVAL, "CLBM_OPT_SINGLE_STEP and CLBM_OPT_FUSED_PAIRS together");
     ctx->options = options;
     return CLBM_OK;
+}
+
+int clbm_fused_pairs(const clbm_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    return fused_pairs(ctx) ? 1 : 0;
 }
 
 int clbm_copy(clbm_ctx *ctx, const void *src, void *dst)

@@ -86,7 +86,7 @@ struct Geom {
     uint32_t P;        // plane stride of state buffers in elements (>= N; padding breaks power-of-two strides)
     FastDiv dnx, dny;
     int32_t wall[3];
-    int32_t moving;    // some wall face moves
+    int32_t moving;    // bit f set when wall face f moves (0 = no moving wall)
     double wu[6][3];   // velocity of wall face (axis a, side s) at [2a + s]; side 1 lies beyond n_a - 1
 };
 
@@ -199,6 +199,16 @@ __device__ __forceinline__ R wall_term(const Nbr &nb, const Geom &g)
     return R(6) * lattice_weight<Q, R>(T) * eu / R(cnt);
 }
 
+// Does the node lie on a moving wall face (face 2 axis + side: side 0 below
+// coordinate 0, side 1 beyond n - 1)?  Links of other nodes cross only resting
+// faces, where the momentum term is zero and is not formed.
+__device__ __forceinline__ bool on_moving_face(const Geom &g, const Nbr &nb)
+{
+    const uint32_t m = static_cast<uint32_t>(g.moving);
+    return ((m & 1u) && !nb.vx[2]) || ((m & 2u) && !nb.vx[0]) || ((m & 4u) && !nb.vy[2]) ||
+           ((m & 8u) && !nb.vy[0]) || ((m & 16u) && !nb.vz[2]) || ((m & 32u) && !nb.vz[0]);
+}
+
 template <typename S, bool CHECK, bool SOLID, bool REV, int Q, typename R>
 __device__ __forceinline__ void gather_links(const S *__restrict__ buf, const Geom &g, uint32_t n, const Nbr &nb,
                                              uint32_t lm, R (&v)[27]);
@@ -245,6 +255,7 @@ __device__ __forceinline__ void gather_links(const S *__restrict__ buf, const Ge
     // adjoint buffers, which are dense [27][N]
     const size_t N = REV ? static_cast<size_t>(g.N) : static_cast<size_t>(g.P);
     constexpr uint32_t es = sizeof(S);
+    const bool mf = !REV && CHECK && g.moving && on_moving_face(g, nb);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         constexpr int i = pop_of_slot(t);
@@ -265,7 +276,7 @@ __device__ __forceinline__ void gather_links(const S *__restrict__ buf, const Ge
                     val = load_at(buf + static_cast<size_t>(ib) * N, n * es);
                 v[t] = static_cast<R>(to_real(val));
                 if constexpr (!REV)
-                    if (g.moving && !ok) v[t] += wall_term<t, Q, R>(nb, g);
+                    if (mf && !ok) v[t] += wall_term<t, Q, R>(nb, g);
             } else {
                 v[t] = static_cast<R>(to_real(load_at(Pi, off * es)));
             }
@@ -279,6 +290,7 @@ __device__ __forceinline__ void scatter(S *__restrict__ buf, const Geom &g, uint
                                         const R (&v)[27])
 {
     const size_t N = g.P;  // state buffer
+    const bool mf = CHECK && g.moving && on_moving_face(g, nb);
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         constexpr int i = pop_of_slot(t);
@@ -293,7 +305,7 @@ __device__ __forceinline__ void scatter(S *__restrict__ buf, const Geom &g, uint
             const bool ok = link_open<t, false, SOLID>(nb, lm, off);
             if constexpr (CHECK) {
                 constexpr int ib = pop_of_slot(26 - t);
-                if (g.moving && !ok) val = to_store<S>(v[t] - wall_term<t, Q, R>(nb, g));
+                if (mf && !ok) val = to_store<S>(v[t] - wall_term<t, Q, R>(nb, g));
                 S *p = ok ? (Pi + off) : (buf + static_cast<size_t>(ib) * N + n);
                 *p = val;
             } else {
@@ -303,7 +315,8 @@ __device__ __forceinline__ void scatter(S *__restrict__ buf, const Geom &g, uint
     });
 }
 
-// Link table for lattices with solid nodes: word n has bit t set when the pull of
+// Link table for lattices with solid nodes (and for walled lattices that take the
+// fused two-step kernel; solid = NULL then): word n has bit t set when the pull of
 // slot t into node n is open (the neighbour n - e exists and is fluid) and bit 13
 // (the rest population) set for every fluid node; solid nodes get 0.  One
 // coalesced 32-bit load per node then replaces 26 dependent mask loads.
@@ -318,9 +331,9 @@ __global__ __launch_bounds__(kBlock) void k_links(Geom g, const uint8_t *__restr
     sfor<0, 27>([&](auto TT) {
         constexpr int t = decltype(TT)::value;
         uint32_t off;
-        if (has_slot<Q>(t) && link_open<t, false, false>(nb, 0u, off) && solid[off] == 0) m |= 1u << t;
+        if (has_slot<Q>(t) && link_open<t, false, false>(nb, 0u, off) && (!solid || solid[off] == 0)) m |= 1u << t;
     });
-    links[n] = solid[n] ? 0u : (m | (1u << 13));
+    links[n] = solid && solid[n] ? 0u : (m | (1u << 13));
 }
 
 template <typename R>
@@ -480,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 }
 
 // ------------------------------------------------------------------ two fused steps (temporal blocking)
-// Two time steps per launch on FP32 lattices without moving walls.  A block
+// Two time steps per launch on FP32 D3Q27 lattices (cascaded collision).  A block
 // owns a 32 x 12 tile of (x, y) columns and marches along a chunk of z planes.
 // For each plane it first runs step t -> t+1 on the tile plus a one-node halo
 // (34 x 14 nodes, pulling from HBM), keeping the results in LDS, and then step
@@ -501,11 +514,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 //
 // With solid nodes or walls (SOLID: the link table holds every node's open
 // links) the bounce-back of Eq. (8) in step t+2 takes the node's own opposite
-// population from step t+1.  The tile's nodes are then stepped a second time by
-// the threads of their own halo positions, which hold the node's e_z = +1 group
-// and link word in registers; the e_z = 0 group of plane z is in LDS, and the
-// e_z = -1 groups alternate between two LDS slots by plane parity so that plane
-// z's stays readable while plane z+1's is written (68.5 KB per block).
+// population from step t+1 (plus the momentum of a moving wall).  Each tile
+// node is then stepped in t+2 by the thread that stepped it in t+1 (threads 0
+// to 383 take the tile, 384 to 475 the halo ring), whose registers hold the
+// node's e_z = +1 group and link word; the e_z = 0 group of plane z is in LDS,
+// and the e_z = -1 groups alternate between two LDS slots by plane parity so
+// that plane z's stays readable while plane z+1's is written (68.5 KB per block).
 constexpr int kT2X = 32, kT2Y = 12;
 constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 476 nodes
 constexpr int kT2Block = (kT2H + 63) / 64 * 64;                             // 512 threads, eight wavefronts
@@ -637,8 +651,15 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             } else if (__all(lm == all_links<27>())) {
                 sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = rf[pulled_at(TT)]; });
             } else {
-                // a blocked link returns the node's own opposite population of step t+1 (Eq. (8))
+                // a blocked link returns the node's own opposite population of step t+1 (Eq. (8)),
+                // plus the momentum of a moving wall as in gather()
                 const int ro = zm(z);
+                Nbr nb;
+                bool mf = false;
+                if (g.moving) {
+                    neighbours_xyz(g, gx, gy, zz, nb);
+                    mf = on_moving_face(g, nb);
+                }
                 sfor<0, 27>([&](auto TT) {
                     constexpr int t = decltype(TT)::value;
                     constexpr int jo = 8 - (3 * sa(t) + sb(t)), co = 2 - sc(t);
@@ -651,7 +672,9 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
                             own = keep2a[jo];
                         else
                             own = rf[((co == 0 ? ro : 1) * 9 + jo) * kT2H + hn];
-                        v[t] = (lm >> t) & 1u ? nbv : own;
+                        const bool open = (lm >> t) & 1u;
+                        v[t] = open ? nbv : own;
+                        if (mf && !open) v[t] += wall_term<t, 27, R>(nb, g);
                     }
                 });
             }

@@ -71,7 +71,7 @@ def test_default_plane_stride():
 
 def test_strerror_and_version():
     L = _lib()
-    assert L.clbm_abi_version() == 4
+    assert L.clbm_abi_version() == 5
     for code, word in [(0, b"success"), (1, b"invalid"), (2, b"rate"), (3, b"storage"), (4, b"HIP"),
                        (5, b"non-finite")]:
         assert word in L.clbm_strerror(code)
@@ -140,6 +140,7 @@ def test_calls_on_null_context_fail_cleanly():
     assert L.clbm_step(None, None, None) == 1
     assert L.clbm_run(None, None, None, 3, None) == 1
     assert L.clbm_set_options(None, 0) == 1
+    assert L.clbm_fused_pairs(None) == 1
     assert L.clbm_moments(None, None, None, None, None, None) == 1
     assert L.clbm_adjoint_step(None, None, None, None, None, None) == 1
     assert L.clbm_destroy(None) == 0

@@ -1,7 +1,7 @@
-"""Fused two-step launches (clbm_run on FP32 cascaded D3Q27 lattices, periodic
-or with solid nodes and walls) are bitwise identical to single steps, across
-ragged tiles, thin lattices, odd step counts, both collision paths, with or
-without a force field, every wall combination, random solids and packed
+"""Fused two-step launches (clbm_run on FP32 cascaded D3Q27 lattices: periodic,
+walled, moving walls, solid nodes) are bitwise identical to single steps,
+across ragged tiles, thin lattices, odd step counts, both collision paths, with
+or without a force field, every wall combination, random solids and packed
 spheres; and they match the oracle."""
 from __future__ import annotations
 
@@ -59,28 +59,53 @@ def test_fused_pairs_without_force_field(rates):
     assert torch.equal(a, b)
 
 
-def test_fused_pairs_apply_to_fp32_lattices_periodic_or_with_solids():
+def test_fused_pairs_apply_to_fp32_cascaded_d3q27_lattices():
     from paper_1801_04586_amd import Lattice
 
     dims = (8, 8, 8)
     sol = workloads.random_solids(dims, 0.1, 9)
-    cases = [("f32", (0, 0, 0), None, None, True), ("f64", (0, 0, 0), None, None, False),
-             ("f16", (0, 0, 0), None, None, False), ("bf16", (0, 0, 0), None, None, False),
-             ("f32", (0, 1, 0), None, None, False), ("f32", (0, 0, 0), sol, None, True),
-             ("f32", (1, 1, 1), sol, None, True), ("f64", (0, 1, 0), sol, None, False),
-             ("f32", (0, 1, 0), sol, {(1, 1): (0.01, 0.0, 0.0)}, False)]
-    for storage, walls, solid, wv, fused in cases:
-        lat = Lattice(dims, walls, storage, RATES, solid=solid, wall_velocity=wv)
-        assert lat.uses_fused_pairs == fused, (storage, walls, solid is not None, wv)
+    lid = {(1, 1): (0.01, 0.0, 0.0)}
+    cases = [("f32", (0, 0, 0), None, None, "d3q27", "cascaded", True),
+             ("f64", (0, 0, 0), None, None, "d3q27", "cascaded", False),
+             ("f16", (0, 0, 0), None, None, "d3q27", "cascaded", False),
+             ("bf16", (0, 0, 0), None, None, "d3q27", "cascaded", False),
+             ("f32", (0, 1, 0), None, None, "d3q27", "cascaded", True),
+             ("f32", (0, 0, 0), sol, None, "d3q27", "cascaded", True),
+             ("f32", (1, 1, 1), sol, None, "d3q27", "cascaded", True),
+             ("f64", (0, 1, 0), sol, None, "d3q27", "cascaded", False),
+             ("f32", (0, 1, 0), sol, lid, "d3q27", "cascaded", True),
+             ("f32", (1, 1, 1), None, lid, "d3q27", "cascaded", True),
+             ("f32", (0, 1, 0), None, None, "d3q19", "cascaded", False),
+             ("f32", (0, 1, 0), None, None, "d3q27", "mrt", False)]
+    for storage, walls, solid, wv, lattice, coll, fused in cases:
+        lat = Lattice(dims, walls, storage, RATES, solid=solid, wall_velocity=wv, lattice=lattice, collision=coll)
+        assert not lat.uses_fused_pairs  # 8^3 is too small to fill the device: single steps by default
+        lat.set_fused_steps(True)
+        assert lat.uses_fused_pairs == fused, (storage, walls, solid is not None, wv, lattice, coll)
+        lat.set_fused_steps(False)
+        assert not lat.uses_fused_pairs
         lat.close()
 
 
-def _run_solid(dims, walls, solid, steps, fused, f0, field, rates=RATES):
+def test_fused_pairs_by_default_only_on_lattices_that_fill_the_device():
+    """Default rule: tile columns (32 x 12) times z chunks of 8 planes must give two blocks per compute unit."""
     from paper_1801_04586_amd import Lattice
 
-    lat = Lattice(dims, walls, "f32", rates, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid)
-    assert lat.uses_fused_pairs
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for dims, walls in (((64, 64, 64), (0, 1, 0)), ((128, 128, 128), (0, 0, 0)), ((256, 96, 64), (1, 1, 1))):
+        blocks = -(-dims[0] // 32) * -(-dims[1] // 12) * max(dims[2] // 8, 1)
+        lat = Lattice(dims, walls, "f32", RATES)
+        assert lat.uses_fused_pairs == (blocks >= 2 * cus), (dims, blocks, cus)
+        lat.close()
+
+
+def _run_solid(dims, walls, solid, steps, fused, f0, field, rates=RATES, wall_velocity=None):
+    from paper_1801_04586_amd import Lattice
+
+    lat = Lattice(dims, walls, "f32", rates, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid,
+                  wall_velocity=wall_velocity)
     lat.set_fused_steps(fused)
+    assert lat.uses_fused_pairs == fused
     lat.set_populations(torch.from_numpy(f0))
     lat.step(steps)
     out = lat.state.clone()
@@ -129,6 +154,53 @@ def test_fused_pairs_with_walls_and_an_all_fluid_mask():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("dims,walls", [((67, 19, 13), (0, 1, 0)), ((33, 9, 40), (1, 1, 1)), ((5, 7, 2), (1, 0, 1)),
+                                        ((40, 12, 3), (0, 0, 1)), ((1, 13, 9), (0, 1, 1))])
+def test_fused_pairs_with_walls_only_are_bitwise_single_steps(dims, walls):
+    g, f0 = _start_walls(dims, walls, 61)
+    field = workloads.gaussian_force(dims, 1e-4, 62)
+    for steps in (2, 5):
+        a, _ = _run_solid(dims, walls, None, steps, True, f0, field)
+        b, _ = _run_solid(dims, walls, None, steps, False, f0, field)
+        assert torch.equal(a, b), (dims, walls, steps)
+
+
+def _moving_faces(walls, seed):
+    rng = np.random.default_rng(seed)
+    return {(a, sd): tuple(0.05 * rng.standard_normal(3)) for a in range(3) if walls[a] for sd in (0, 1)}
+
+
+@pytest.mark.parametrize("dims,walls,frac", [((38, 14, 9), (0, 1, 0), 0.0), ((35, 13, 11), (1, 1, 1), 0.0),
+                                             ((35, 13, 11), (1, 1, 1), 0.15), ((20, 30, 7), (0, 1, 1), 0.1)])
+def test_fused_pairs_with_moving_walls_are_bitwise_single_steps(dims, walls, frac):
+    """Every face of every walled axis moves, so edge and corner links cross two or three moving faces."""
+    g, f0 = _start_walls(dims, walls, 71)
+    solid = workloads.random_solids(dims, frac, 72) if frac else None
+    wv = _moving_faces(walls, 73)
+    for steps in (2, 3):
+        a, _ = _run_solid(dims, walls, solid, steps, True, f0, None, RATES_H1, wv)
+        b, _ = _run_solid(dims, walls, solid, steps, False, f0, None, RATES_H1, wv)
+        assert torch.equal(a, b), (dims, walls, frac, steps)
+
+
+def test_fused_run_with_moving_walls_matches_oracle():
+    dims, walls = (36, 15, 8), (1, 1, 1)
+    g, f0 = _start_walls(dims, walls, 81)
+    wv = _moving_faces(walls, 82)
+    from paper_1801_04586_amd import Lattice
+
+    lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, -3e-6, 2e-6), wall_velocity=wv)
+    lat.set_fused_steps(True)
+    assert lat.uses_fused_pairs
+    lat.set_populations(torch.from_numpy(f0))
+    start = lat.populations().cpu().numpy()
+    lat.step(4)
+    got = lat.populations().cpu().numpy()
+    ref = oracle.run(g, start, RATES, 4, force=(1e-5, -3e-6, 2e-6), wall_velocity=wv)
+    assert np.max(np.abs(got - ref)) < 1e-7
+    lat.close()
+
+
 def test_fused_run_with_solids_matches_oracle():
     dims, walls = (37, 14, 9), (0, 1, 0)
     g, f0 = _start_walls(dims, walls, 51)
@@ -137,6 +209,7 @@ def test_fused_run_with_solids_matches_oracle():
     from paper_1801_04586_amd import Lattice
 
     lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid)
+    lat.set_fused_steps(True)
     assert lat.uses_fused_pairs
     lat.set_populations(torch.from_numpy(f0))
     start = lat.populations().cpu().numpy()
@@ -156,6 +229,8 @@ def test_fused_run_matches_oracle():
     from paper_1801_04586_amd import Lattice
 
     lat = Lattice(dims, (0, 0, 0), "f32", RATES, force=(1e-5, -3e-6, 2e-6), force_field=field)
+    lat.set_fused_steps(True)
+    assert lat.uses_fused_pairs
     lat.set_populations(torch.from_numpy(f0))
     start = lat.populations().cpu().numpy()
     lat.step(4)
