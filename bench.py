@@ -469,6 +469,26 @@ def main():
             "bytes_per_node": ab, "frac": round(ab * an / (ams * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "solid_fraction": round(float(mask.mean()), 4)}
         log(f"[bench] adjoint: {variants['adjoint_porous_256x128x128_f32']}")
+        # end to end: gradient of the flow loss on the crop, T = 40 steps, checkpoint every K = 20
+        from paper_1801_04586_amd.adjoint import flow_loss
+
+        Ta, Ka = 40, 20
+        s0a = la.state.clone()
+        Fta = torch.from_numpy(Fa).to(dev, torch.float32)
+        sta = torch.from_numpy(workloads.rates(0.02))
+        times = []
+        for _ in range(3):
+            Fr, sr = Fta.clone().requires_grad_(True), sta.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            flow_loss(Fr, sr, la, s0a, ut, Ta, Ka).backward()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        tg = min(times)
+        variants["adjoint_porous_256x128x128_f32"].update({
+            "gradient_T40_K20_seconds": round(tg, 4),
+            "gradient_node_updates_per_s_M": round(an * Ta * 3 / tg / 1e6, 1)})
+        log(f"[bench] adjoint gradient: {variants['adjoint_porous_256x128x128_f32']}")
         la.close()
         del la, lam, lam2, gF
         torch.cuda.empty_cache()

@@ -6,10 +6,12 @@ lattice started from ``state0``, with the per-node body-force field and the ten
 relaxation rates of Eq. (13) as differentiable inputs.  The backward pass runs
 the hand-written adjoint kernels (``clbm_loss_seed``, ``clbm_adjoint_step``):
 
-  * forward: T steps, a copy of the state kept every K steps (checkpoints);
+  * forward: T steps through clbm_run (fused step pairs where it uses them),
+    a copy of the state kept every K steps (checkpoints);
   * backward: segments from last to first; each segment's K states are
-    recomputed from its checkpoint with the forward kernel (bitwise identical
-    to the original run), then the adjoint steps walk back through them.
+    recomputed from its checkpoint by single steps (bitwise identical to the
+    original run, fused pairs being bitwise two single steps), then the
+    adjoint steps walk back through them.
 
 Memory: ceil(T/K) checkpoints + K segment states + two adjoint buffers.
 """
@@ -36,13 +38,15 @@ class _FlowLoss(torch.autograd.Function):
         a, b = torch.empty_like(state0), torch.empty_like(state0)
         c.copy(state0, a)
         ckpts = []
-        for t in range(nsteps):
-            if t % K == 0:
-                ck = torch.empty_like(a)
-                c.copy(a, ck)
-                ckpts.append(ck)
-            c.step(a, b)
-            a, b = b, a
+        t = 0
+        while t < nsteps:  # a checkpoint every K steps; clbm_run may fuse the steps in between
+            ck = torch.empty_like(a)
+            c.copy(a, ck)
+            ckpts.append(ck)
+            n = min(K, nsteps - t)
+            if c.run(a, b, n):
+                a, b = b, a
+            t += n
         ut = u_target.detach().to(device=lat.device, dtype=lat.real).contiguous()
         lam = torch.empty((27,) + lat.shape, dtype=lat.real, device=lat.device)
         dJdF = torch.zeros((3,) + lat.shape, dtype=lat.real, device=lat.device)
