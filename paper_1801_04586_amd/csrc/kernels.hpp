@@ -196,7 +196,8 @@ __device__ __forceinline__ R wall_term(const Nbr &nb, const Geom &g)
         if (!nb.vz[sc(T)]) add(4 + (sc(T) == 0 ? 1 : 0));
     if (cnt == 0) return R(0);
     const R eu = R(sa(T) - 1) * ux + R(sb(T) - 1) * uy + R(sc(T) - 1) * uz;
-    return R(6) * lattice_weight<Q, R>(T) * eu / R(cnt);
+    const R mean = cnt == 1 ? R(1) : (cnt == 2 ? R(0.5) : R(1.0 / 3.0));  // 1 / faces crossed
+    return R(6) * lattice_weight<Q, R>(T) * eu * mean;
 }
 
 // Does the node lie on a moving wall face (face 2 axis + side: side 0 below
