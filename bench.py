@@ -548,6 +548,43 @@ def main():
             "kind": "oracle",
             "sample": f"{wd[0]}x{wd[1]}x{wd[2]} window of the {L}^3 Kolmogorov lattice, {nsteps} steps, FP64 dense "
                       f"27x27 oracle, {tc:.1f} s"}
+        budget = args.cpu_seconds / 2
+
+        def timed_run(geom, f, rates_, max_steps, **kw):
+            # one step to size the run, then as many as fit the budget (at most max_steps)
+            t0 = time.perf_counter()
+            f = oracle.step(geom, f, rates_, **kw)
+            t1 = time.perf_counter() - t0
+            n = max(1, min(max_steps, int(budget / max(t1, 1e-4))))
+            t0 = time.perf_counter()
+            for _ in range(n):
+                f = oracle.step(geom, f, rates_, **kw)
+            dt = time.perf_counter() - t0
+            return geom.n * n / dt / 1e6, n, dt
+
+        # one core, a smaller window of the same workload
+        nthreads = oracle.num_threads()
+        oracle.set_num_threads(1)
+        w1 = (64, 64, 16)
+        g1 = oracle.Geometry(dims, (0, 0, 0), (0, 0, 0), w1)
+        s1 = (slice(0, w1[2]), slice(0, w1[1]), slice(0, w1[0]))
+        f1 = oracle.init(g1, None, np.ascontiguousarray(u0[(slice(None),) + s1]))
+        m1, n1, d1 = timed_run(g1, f1, rates, 50, force_field=np.ascontiguousarray(F[(slice(None),) + s1]))
+        oracle.set_num_threads(nthreads)
+        result["cpu_baseline"]["single_core"] = {
+            "value": round(m1, 4), "cores": 1,
+            "sample": f"{w1[0]}x{w1[1]}x{w1[2]} window of the same lattice, {n1} steps, {d1:.1f} s"}
+        # the force-driven channel (16x32x16, FP64, 3000 steps) and the 128^3 Taylor-Green vortex, all cores
+        pc = workloads.POISEUILLE
+        gp = oracle.Geometry(pc.dims, pc.walls)
+        mp, npo, dp_ = timed_run(gp, oracle.init(gp), pc.rates(), pc.steps, force=pc.force_uniform)
+        tc2 = workloads.TGV128
+        gt = oracle.Geometry(tc2.dims, tc2.walls)
+        rt0, ut0 = workloads.taylor_green_3d(tc2.dims, 0.04)
+        mt, ntg, dtg = timed_run(gt, oracle.init(gt, rt0, ut0), tc2.rates(), tc2.steps)
+        result["cpu_baseline"]["other_workloads"] = {
+            pc.name: {"value": round(mp, 4), "steps": npo, "seconds": round(dp_, 2)},
+            tc2.name: {"value": round(mt, 4), "steps": ntg, "seconds": round(dtg, 2)}}
         log(f"[bench] cpu baseline: {result['cpu_baseline']}")
 
     result["context"] = {

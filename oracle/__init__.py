@@ -71,6 +71,8 @@ def lib():
         L.orc_adjoint_step.argtypes = [ip, dp, dp, dp, u8, dp, dp, dp, dp, dp]
         L.orc_loss_seed.argtypes = [ip, dp, dp, u8, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = None
         for name in ("orc19_matrix_M", "orc19_matrix_Minv"):
             getattr(L, name).argtypes = [dp]
         L.orc19_matrix_K.argtypes = [dp, dp]
@@ -97,6 +99,11 @@ def lib():
 def num_threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's later loops (n >= 1)."""
+    lib().orc_set_num_threads(int(n))
 
 
 # --------------------------------------------------------------------------- helpers

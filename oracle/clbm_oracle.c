@@ -719,6 +719,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads for the following parallel loops (n >= 1); no effect without OpenMP. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ======================================================================== */
 /* D3Q19 cascaded LBM of Appendix A                                          */
 /* ======================================================================== */

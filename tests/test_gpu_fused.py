@@ -87,6 +87,22 @@ def test_fused_pairs_apply_to_fp32_cascaded_d3q27_lattices():
         lat.close()
 
 
+def test_fused_option_flags():
+    from paper_1801_04586_amd import Lattice
+    from paper_1801_04586_amd.clbm import ClbmError
+
+    lat = Lattice((8, 8, 8), (0, 0, 0), "f32", RATES)
+    for opts, fused in ((0, False), (1, False), (2, True)):
+        lat.ctx.set_options(opts)
+        assert lat.uses_fused_pairs == fused, opts
+    for bad in (3, 4, 0x80000000):
+        with pytest.raises(ClbmError) as e:
+            lat.ctx.set_options(bad)
+        assert e.value.code == 1
+    assert lat.uses_fused_pairs  # a refused call leaves the options as they were
+    lat.close()
+
+
 def test_fused_pairs_by_default_only_on_lattices_that_fill_the_device():
     """Default rule: tile columns (32 x 12) times z chunks of 8 planes must give two blocks per compute unit."""
     from paper_1801_04586_amd import Lattice
