@@ -91,6 +91,20 @@ def time_steps(torch, lat, steps, reps=9):
     return trimmed_mean(out)
 
 
+def graph_of_steps(torch, lat, steps):
+    """A HIP graph (torch.cuda.CUDAGraph) of lat.step(steps), captured on a side stream.  With an even
+    number of launches the state ends in the buffer it started in, so every replay advances it."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            lat.step(steps)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    return graph
+
+
 def kolmogorov_inputs(dims):
     import workloads
 
@@ -361,8 +375,19 @@ def main():
                 lv.step(10000)
                 torch.cuda.synchronize()
                 row[name] = round(time.perf_counter() - t0, 5)
+                # the same 10 000 steps as 100 replays of a HIP graph of 100 launches (launch-bound lattices)
+                graph = graph_of_steps(torch, lv, 100)
+                graph.replay()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(100):
+                    graph.replay()
+                torch.cuda.synchronize()
+                row[name + "_graph"] = round(time.perf_counter() - t0, 5)
+                del graph
                 lv.close()
             row["t_C/t_S"] = round(row["t_C"] / row["t_S"], 3)
+            row["t_C/t_S_graph"] = round(row["t_C_graph"] / row["t_S_graph"], 3)
             table1[f"5x{ny}x5"] = row
         variants["table_I_shear_wave_10000_steps_f64"] = table1
         log(f"[bench] Table I workload: {table1}")
