@@ -254,3 +254,27 @@ def test_fused_run_matches_oracle():
     ref = oracle.run(g, start, RATES, 4, force=(1e-5, -3e-6, 2e-6), force_field=lat.force_field.double().cpu().numpy())
     assert np.max(np.abs(got - ref)) < 1e-7
     lat.close()
+
+
+@pytest.mark.parametrize("dims,walls,frac", [((67, 19, 13), (0, 0, 0), 0.0), ((45, 26, 9), (1, 1, 1), 0.2)],
+                         ids=["periodic", "walls_solids"])
+def test_fused_launch_writes_every_fluid_entry_and_no_padding(dims, walls, frac):
+    """The output buffer of one fused launch is filled with NaN first: afterwards every fluid entry is
+    finite and the plane padding is still NaN."""
+    g, f0 = _start_walls(dims, walls, 101)
+    solid = workloads.random_solids(dims, frac, 102) if frac else None
+    from paper_1801_04586_amd import Lattice
+
+    lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, 0.0, 0.0), solid=solid)
+    lat.set_fused_steps(True)
+    lat.set_populations(torch.from_numpy(f0))
+    lat.other.fill_(float("nan"))
+    out = lat.other
+    lat.step(2)
+    assert lat.state.data_ptr() == out.data_ptr()
+    n = int(np.prod(dims))
+    body = out[:, :n].reshape((27,) + g.shape).cpu().numpy()
+    fl = np.ones(g.shape, bool) if solid is None else solid == 0
+    assert np.isfinite(body[:, fl]).all()
+    assert torch.isnan(out[:, n:]).all()
+    lat.close()
