@@ -11,8 +11,8 @@
  *    N = nx * ny * nz must be below 2^31, and N times the widest element a
  *    plane holds (8 bytes for CLBM_F64 storage, 4 otherwise: state, adjoint
  *    and force planes) must not exceed 4 GiB, since kernels address a plane
- *    with 32-bit byte offsets: N <= 2^29 for FP64, N <= 2^30 otherwise.  Lattice units: dx = dt = 1,
- *    c_s^2 = 1/3 (Sec. II A).
+ *    with 32-bit byte offsets: N <= 2^29 for FP64, N <= 2^30 otherwise.
+ *    Lattice units: dx = dt = 1, c_s^2 = 1/3 (Sec. II A).
  *  - Axes: wall[a] = 0 makes axis a periodic; wall[a] = 1 puts stationary
  *    half-way bounce-back walls at both ends of axis a (Sec. III): a population
  *    leaving fluid node x towards a wall or a solid node returns to x,
