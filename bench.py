@@ -200,7 +200,10 @@ def main():
     kname = "k_step2<float, force field> (two fused steps)" if fused else "k_step<float, periodic, force field>"
 
     result = {
-        "metric": "MLUPS (FP32-storage fused D3Q27 cascaded-LBM step) and fraction of HBM roofline",
+        # the headline metric; value = FP32-storage MLUPS of the fused D3Q27 cascaded step, roofline.frac its
+        # HBM fraction; FP64/FP16/BF16 storage, the adjoint and the errors against FP64 are under variants
+        # and accuracy_vs_f64
+        "metric": "MLUPS & % HBM roofline: FP64 vs FP32/FP16-storage fwd, adjoint MLUPS, at stated err",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
