@@ -5,16 +5,20 @@ Workload (the roofline and precision case): Kolmogorov-forced flow on a 512^3
 periodic lattice, F_x = 1e-5 sin(2 pi 4 y / 512) as a per-node FP32 field,
 nu = 0.005, seeded U(-1e-3, 1e-3) velocity perturbation, populations stored as
 FP32 deviations f - w with FP32 arithmetic.  A "step" is one time step of the
-whole lattice (one launch of the fused collide-and-stream kernel); the metric
-is MLUPS (million lattice-node updates per second) and the fraction of the
-HBM roofline.  Inputs are resident in HBM before the timed region.
+whole lattice (pairs of steps run as one launch of the fused two-step
+collide-and-stream kernel); the metric is MLUPS (million lattice-node updates
+per second) and the fraction of the HBM roofline.  Inputs are resident in HBM
+before the timed region.
 
 Also reported from the same run (each timed with HIP events, trimmed mean of
-9 repetitions as in the paper's Table I protocol): the FP64, FP16 and BF16
-storage variants on the same lattice, the plain kernel on the 128^3
-Taylor-Green case, the adjoint step on a 256x128x128 porous crop, the
-velocity error of every storage type against FP64 after 500 steps, and the
-FP64 CPU oracle on a bounded sample of the same workload.
+9 repetitions as in the paper's Table I protocol): the single-step kernel and
+dense planes on the same lattice; FP64, FP16 and BF16 storage; the MRT of
+Appendix B and the D3Q19 scheme of Appendix A; the lid-driven cavity 256^3;
+Table I's shear-wave workload (cascaded against SRT, also from HIP graph
+replays); the 128^3 Taylor-Green case; the porous duct 640x320x320; the
+adjoint step and the end-to-end gradient on its 256x128x128 crop and on the
+64^3 channel; the velocity error of every storage type against FP64 after
+500 steps; and the FP64 CPU oracle on bounded samples.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
