@@ -63,6 +63,38 @@ def test_adjoint_step_matches_oracle(walls, solid_frac, storage, tol):
     lat.close()
 
 
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-5)])
+def test_adjoint_step_on_a_lattice_whose_rate_sums_take_the_two_stage_fold(storage, tol):
+    """96x80x72 = 552 960 nodes: 2160 blocks of per-block dJ/ds partials, more than the 2048 that one
+    reduction pass takes, so the sums go through the fixed-order fold first."""
+    dims, walls = (96, 80, 72), (0, 1, 1)
+    g, f0, field, solid = _case(dims, walls, 21, 0.1)
+    force = (1e-5, -2e-5, 5e-6)
+    lat = _lattice(dims, walls, storage, force=force, field=field, solid=solid)
+    lat.set_populations(torch.from_numpy(f0))
+    f_state = lat.populations().cpu().numpy()
+    lam_next = np.random.default_rng(7).normal(0, 1, (27,) + g.shape)
+    real = torch.float64 if storage == "f64" else torch.float32
+    ln = torch.from_numpy(lam_next).to("cuda", real).contiguous()
+    lam_next_used = ln.double().cpu().numpy()
+    lo = torch.empty_like(ln)
+    gF = torch.zeros((3,) + g.shape, dtype=real, device="cuda")
+    gs = torch.zeros(10, dtype=torch.float64, device="cuda")
+    lat.ctx.adjoint_step(lat.state, ln, lo, gF, gs)
+    gs2 = torch.zeros(10, dtype=torch.float64, device="cuda")
+    lat.ctx.adjoint_step(lat.state, ln, lo, gF, gs2)
+    assert torch.equal(gs, gs2)  # deterministic
+    ref_lam, ref_gF, ref_gs = oracle.adjoint_step(g, f_state, lam_next_used, RATES, force=force,
+                                                  force_field=lat.force_field.double().cpu().numpy(), solid=solid)
+    fl = solid == 0
+    got = lo.double().cpu().numpy()
+    assert np.max(np.abs(got[:, fl] - ref_lam[:, fl])) <= tol * np.max(np.abs(ref_lam[:, fl]))
+    gsg = gs.cpu().numpy()
+    assert gsg[0] == 0.0 and gsg[1] == 0.0
+    assert np.max(np.abs(gsg[2:] - ref_gs[2:])) <= tol * np.max(np.abs(ref_gs[2:])) * 10
+    lat.close()
+
+
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-13), ("f32", 1e-6)])
 def test_loss_seed_matches_oracle(storage, tol):
     dims, walls = (9, 8, 4), (0, 1, 0)
