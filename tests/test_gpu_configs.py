@@ -211,6 +211,34 @@ def test_kolmogorov_512_linear_spinup_fp32(kolmogorov_inputs):
     lat.close()
 
 
+def test_kolmogorov_512_storage_errors_against_fp64_after_500_steps(kolmogorov_inputs):
+    """The precision workload: velocity after 500 steps with FP32, FP16 and BF16 deviation storage
+    (FP32 arithmetic) against FP64 storage on the same inputs.  FP32 meets the 1e-5 relative target;
+    FP16 and BF16 keep the errors their 11- and 8-bit significands allow (measured 2.8e-4 and 1.9e-2)."""
+    cfg = workloads.KOLMOGOROV512
+    u0, F = kolmogorov_inputs
+    lat = _lattice(cfg.dims, cfg.walls, "f64", cfg.rates(), field=F)
+    lat.init(None, u0)
+    lat.step(cfg.steps)
+    u64 = lat.moments()[1]
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    nrm = torch.linalg.vector_norm(u64)
+    for storage, tol in (("f32", 1e-5), ("f16", 1e-3), ("bf16", 5e-2)):
+        ls = _lattice(cfg.dims, cfg.walls, storage, cfg.rates(), field=F)
+        ls.init(None, u0)
+        ls.step(cfg.steps)
+        _, u, _, nbad = ls.moments()
+        assert nbad == 0
+        err = (torch.linalg.vector_norm(u - u64) / nrm).item()
+        print(f"Kolmogorov 512^3, {storage} storage: L2-relative velocity error {err:.3e}")
+        assert err < tol, (storage, err)
+        ls.close()
+        del ls, u
+        torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------------------- porous duct 640x320x320
 @pytest.fixture(scope="module")
 def porous_mask():
