@@ -85,6 +85,7 @@ def lib():
         L.orc19_collide.argtypes = [dp, dp, dp, dp]
         L.orc19_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.orc19_step.argtypes = [ip, dp, dp, dp, u8, dp, dp]
+        L.orc19_step_ex.argtypes = [ip, dp, dp, dp, u8, dp, dp, dp]
         L.orc19_macro.argtypes = [ip, dp, dp, u8, dp, dp, dp]
         L.orc19_init.argtypes = [ip, dp, dp, dp]
         L.orc_mrt_feq.argtypes = [ctypes.c_double, dp, dp]
@@ -389,15 +390,17 @@ def step(geom: Geometry, f, s, force=(0.0, 0.0, 0.0), force_field=None, solid=No
     """One time step (Steps 1-4); returns the pre-collision populations at t+1.
 
     model "mrt": the raw-moment MRT of Appendix B (D3Q27); wall_velocity: moving
-    walls, {(axis, side): (ux, uy, uz)} (D3Q27)."""
+    walls, {(axis, side): (ux, uy, uz)}."""
     f = _f64(f)
     assert f.shape[0] == _q(lattice) and model in MODELS
     out = np.empty_like(f)
     solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
     args = (_d(_rates(s)), _d(_vec3(force)), _d(_f64(force_field)), _u8(solid))
-    if model == "cascaded" and wall_velocity is None:
-        fn = lib().orc_step if lattice == "d3q27" else lib().orc19_step
-        rc = fn(geom.ptr(), *args, _d(f), _d(out))
+    if lattice == "d3q19":
+        assert model == "cascaded"
+        rc = lib().orc19_step_ex(geom.ptr(), *args, _d(_wall_u(wall_velocity)), _d(f), _d(out))
+    elif model == "cascaded" and wall_velocity is None:
+        rc = lib().orc_step(geom.ptr(), *args, _d(f), _d(out))
     else:
         assert lattice == "d3q27"
         rc = lib().orc_step_ex(geom.ptr(), *args, _d(_wall_u(wall_velocity)), MODELS.index(model), _d(f), _d(out))

@@ -940,9 +940,19 @@ int orc19_equilibrium(double rho, const double *u, double *feq)
     return 0;
 }
 
-/* One D3Q19 time step; arguments as orc_step, populations [19][n]. */
-int orc19_step(const int *geom, const double *s, const double *Fu, const double *Ff,
-               const uint8_t *solid, const double *fin, double *fout)
+/* D3Q19 rest-state weights (Appendix A): 1/3, 1/18, 1/36 by the number of nonzero components. */
+static double weight19(int i)
+{
+    const int k = abs(EX19[i]) + abs(EY19[i]) + abs(EZ19[i]);
+    return k == 0 ? 1.0 / 3.0 : (k == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+/* One D3Q19 time step; arguments as orc_step, populations [19][n].  wall_u: velocities of the
+ * wall faces as for orc_step_ex (the D3Q27 MRT section below), or NULL for walls at rest; a link
+ * leaving fluid node x through moving faces returns reversed with -2 w_i (e_i . u_w)/c_s^2,
+ * u_w the mean velocity of the faces it crosses. */
+int orc19_step_ex(const int *geom, const double *s, const double *Fu, const double *Ff,
+                  const uint8_t *solid, const double *wall_u, const double *fin, double *fout)
 {
     orc_geom G;
     orc19_consts k;
@@ -967,23 +977,45 @@ int orc19_step(const int *geom, const double *s, const double *Fu, const double 
         for (int i = 0; i < Q19; ++i) f[i] = fin[(long)i * n + node];
         force_at(Fu, Ff, n, node, F);
         collide_node19(&k, f, F, fs);
+        const int c[3] = {x, y, z};
         for (int i = 0; i < Q19; ++i) {
-            const int lx = locate(&G, 0, G.o[0] + x + EX19[i]);
-            const int ly = locate(&G, 1, G.o[1] + y + EY19[i]);
-            const int lz = locate(&G, 2, G.o[2] + z + EZ19[i]);
-            if (lx == -2 || ly == -2 || lz == -2) continue;
+            const int ei[3] = {EX19[i], EY19[i], EZ19[i]};
+            int l[3], partial = 0, beyond = 0;
+            double uw[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < 3; ++a) {
+                const int gc = G.o[a] + c[a] + ei[a];
+                l[a] = locate(&G, a, gc);
+                if (l[a] == -2) partial = 1;
+                if (l[a] == -1) {
+                    ++beyond;
+                    if (wall_u)
+                        for (int b = 0; b < 3; ++b) uw[b] += wall_u[3 * (2 * a + (gc < 0 ? 0 : 1)) + b];
+                }
+            }
+            if (partial) continue;
             long tgt = -1;
-            if (lx >= 0 && ly >= 0 && lz >= 0) {
-                tgt = (long)lx + (long)G.w[0] * ((long)ly + (long)G.w[1] * lz);
+            if (!beyond) {
+                tgt = (long)l[0] + (long)G.w[0] * ((long)l[1] + (long)G.w[1] * l[2]);
                 if (solid && solid[tgt]) tgt = -1;
             }
-            if (tgt >= 0)
+            if (tgt >= 0) {
                 fout[(long)i * n + tgt] = fs[i];
-            else
-                fout[(long)opp[i] * n + node] = fs[i];
+            } else {
+                double corr = 0.0;
+                if (beyond)
+                    corr = 2.0 * weight19(i) * (ei[0] * uw[0] + ei[1] * uw[1] + ei[2] * uw[2]) / (beyond * CS2);
+                fout[(long)opp[i] * n + node] = fs[i] - corr;
+            }
         }
     }
     return 0;
+}
+
+/* One D3Q19 time step with walls at rest. */
+int orc19_step(const int *geom, const double *s, const double *Fu, const double *Ff,
+               const uint8_t *solid, const double *fin, double *fout)
+{
+    return orc19_step_ex(geom, s, Fu, Ff, solid, NULL, fin, fout);
 }
 
 /* Eq. (9) on every D3Q19 node. */

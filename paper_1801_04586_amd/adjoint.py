@@ -33,7 +33,8 @@ class _FlowLoss(torch.autograd.Function):
             raise ValueError("nsteps >= 0 and K >= 1 required")
         field = force_field.detach().to(device=lat.device, dtype=lat.real).contiguous()
         lat.set_force(lat.force, field, lat.force_scale)
-        lat.set_rates(rates.detach().cpu().to(torch.float64).numpy())
+        rate_values = rates.detach().cpu().to(torch.float64).numpy().copy()
+        lat.set_rates(rate_values)
         c = lat.ctx
         a, b = torch.empty_like(state0), torch.empty_like(state0)
         c.copy(state0, a)
@@ -55,6 +56,8 @@ class _FlowLoss(torch.autograd.Function):
         ctx.lat, ctx.nsteps, ctx.K = lat, nsteps, K
         ctx.ckpts, ctx.lam, ctx.dJdF = ckpts, lam, dJdF
         ctx.field = field
+        # the lattice may be reconfigured before backward runs: keep what this forward pass used
+        ctx.rates, ctx.force, ctx.force_scale = rate_values, lat.force, lat.force_scale
         ctx.rates_meta = (rates.dtype, rates.device)
         ctx.ff_meta = (force_field.dtype, force_field.device)
         return J[0]
@@ -63,7 +66,8 @@ class _FlowLoss(torch.autograd.Function):
     def backward(ctx, gJ):
         lat, nsteps, K = ctx.lat, ctx.nsteps, ctx.K
         c = lat.ctx
-        lat.set_force(lat.force, ctx.field, lat.force_scale)
+        lat.set_force(ctx.force, ctx.field, ctx.force_scale)
+        lat.set_rates(ctx.rates)
         lam, dJdF = ctx.lam, ctx.dJdF
         lam2 = torch.empty_like(lam)
         dJds = torch.zeros(10, dtype=torch.float64, device=lat.device)
@@ -79,7 +83,8 @@ class _FlowLoss(torch.autograd.Function):
                 c.adjoint_step(seg[t - t0], lam, lam2, dJdF, dJds)
                 lam, lam2 = lam2, lam
         g = gJ.to(torch.float64)
-        gF = (dJdF.to(torch.float64) * g).to(dtype=ctx.ff_meta[0], device=ctx.ff_meta[1])
+        # the kernels accumulate dJ/dF for the total force F = uniform + force_scale * field
+        gF = (dJdF.to(torch.float64) * (g * ctx.force_scale)).to(dtype=ctx.ff_meta[0], device=ctx.ff_meta[1])
         gs = (dJds * g).to(dtype=ctx.rates_meta[0], device=ctx.rates_meta[1])
         ctx.ckpts = None
         return gF, gs, None, None, None, None, None
@@ -102,7 +107,8 @@ def initial_gradient(lat: Lattice, state0: torch.Tensor, u_target: torch.Tensor,
     lam = torch.empty((27,) + lat.shape, dtype=lat.real, device=lat.device)
     lam2 = torch.empty_like(lam)
     J = torch.zeros(1, dtype=torch.float64, device=lat.device)
-    c.loss_seed(states[-1], u_target, lam, None, J)
+    ut = u_target.detach().to(device=lat.device, dtype=lat.real).contiguous()
+    c.loss_seed(states[-1], ut, lam, None, J)
     for t in range(int(nsteps) - 1, -1, -1):
         c.adjoint_step(states[t], lam, lam2, None, None)
         lam, lam2 = lam2, lam

@@ -29,6 +29,7 @@ LATTICE = {"d3q27": CLBM_D3Q27, "d3q19": CLBM_D3Q19}
 LATTICE_Q = {"d3q27": 27, "d3q19": 19}
 CLBM_CASCADED, CLBM_MRT = 0, 1
 COLLISION = {"cascaded": CLBM_CASCADED, "mrt": CLBM_MRT}
+_STORAGE_DTYPE = {STORAGE[k]: v for k, v in STORAGE_TORCH.items()}
 
 
 class ClbmError(RuntimeError):
@@ -140,6 +141,9 @@ class Context:
         """Pointer of a state buffer, after checking that it holds Q x P elements of the storage type."""
         if t is None:
             raise ValueError("state buffer is None")
+        want = _STORAGE_DTYPE[self.desc.storage]
+        if t.dtype != want:
+            raise ValueError(f"state buffer has dtype {t.dtype}, {want} needed (the storage type)")
         if t.numel() * t.element_size() < self.state_bytes:
             raise ValueError(f"state buffer of {t.numel() * t.element_size()} bytes, {self.state_bytes} needed "
                              "(Q x plane_stride elements)")
@@ -219,11 +223,35 @@ class Context:
         self._call("clbm_sample_populations", self._state(state), _ptr(nodes), ctypes.c_int32(int(nodes.numel())),
                    _ptr(out))
 
+    def _buf(self, t: Optional[torch.Tensor], name: str, dtype: torch.dtype, numel: int, optional: bool = False):
+        """Pointer of an adjoint-side buffer after checking its dtype and element count (the library
+        reads and writes exactly that many elements of that type)."""
+        if t is None:
+            if optional:
+                return None
+            raise ValueError(f"{name} is None")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} has dtype {t.dtype}, {dtype} needed")
+        if t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, {numel} needed")
+        return _ptr(t)
+
+    @property
+    def adjoint_dtype(self) -> torch.dtype:
+        """Type of lambda, dJ/dF and the loss target: FP64 for FP64 storage, FP32 otherwise."""
+        return torch.float64 if self.desc.storage == CLBM_F64 else torch.float32
+
     def adjoint_step(self, state_t, lam_next, lam_out, dJdF=None, dJds=None):
-        self._call("clbm_adjoint_step", self._state(state_t), _ptr(lam_next), _ptr(lam_out), _ptr(dJdF), _ptr(dJds))
+        n, r = self.desc.nx * self.desc.ny * self.desc.nz, self.adjoint_dtype
+        self._call("clbm_adjoint_step", self._state(state_t), self._buf(lam_next, "lam_next", r, 27 * n),
+                   self._buf(lam_out, "lam_out", r, 27 * n), self._buf(dJdF, "dJdF", r, 3 * n, True),
+                   self._buf(dJds, "dJds", torch.float64, 10, True))
 
     def loss_seed(self, state, u_target, lam_out, dJdF=None, J=None):
-        self._call("clbm_loss_seed", self._state(state), _ptr(u_target), _ptr(lam_out), _ptr(dJdF), _ptr(J))
+        n, r = self.desc.nx * self.desc.ny * self.desc.nz, self.adjoint_dtype
+        self._call("clbm_loss_seed", self._state(state), self._buf(u_target, "u_target", r, 3 * n),
+                   self._buf(lam_out, "lam_out", r, 27 * n), self._buf(dJdF, "dJdF", r, 3 * n, True),
+                   self._buf(J, "J", torch.float64, 1, True))
 
 
 def wall_velocity_array(wall_velocity) -> np.ndarray:

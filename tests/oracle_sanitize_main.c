@@ -16,6 +16,8 @@ int orc_step(const int *geom, const double *s, const double *Fu, const double *F
              const double *fin, double *fout);
 int orc19_step(const int *geom, const double *s, const double *Fu, const double *Ff, const uint8_t *solid,
                const double *fin, double *fout);
+int orc19_step_ex(const int *geom, const double *s, const double *Fu, const double *Ff, const uint8_t *solid,
+                  const double *wall_u, const double *fin, double *fout);
 int orc_step_ex(const int *geom, const double *s, const double *Fu, const double *Ff, const uint8_t *solid,
                 const double *wall_u, int model, const double *fin, double *fout);
 int orc_macro(const int *geom, const double *Fu, const double *Ff, const uint8_t *solid, const double *f,
@@ -116,6 +118,8 @@ static void run_case(const int *geom, int with_solids, int with_field)
     check(orc19_step(geom, s, Fu, F, sol, f, g), "orc19_step");
     check(orc19_macro(geom, Fu, F, sol, g, rho, u), "orc19_macro");
     check_finite(g, 19 * nw, "d3q19 state");
+    check(orc19_step_ex(geom, s, Fu, F, sol, wall_u, g, f), "orc19_step_ex");
+    check_finite(f, 19 * nw, "d3q19 state, moving walls");
 
     free(rho0), free(u0), free(Ff), free(ut), free(solid), free(f), free(g), free(lam), free(lam2);
     free(rho), free(u), free(gF);

@@ -30,8 +30,10 @@ def _case(dims, walls, seed, solid_frac):
 
 
 @pytest.mark.parametrize("walls,solid_frac", [((0, 0, 0), 0.0), ((0, 1, 0), 0.0), ((1, 1, 1), 0.2)])
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-5)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-5), ("f16", 2e-5), ("bf16", 2e-5)])
 def test_adjoint_step_matches_oracle(walls, solid_frac, storage, tol):
+    """One adjoint step against the oracle's exact discrete adjoint at the populations the kernel reads
+    (the stored state, already rounded to the storage type); FP32 arithmetic for FP32/FP16/BF16."""
     dims = (7, 6, 5)
     g, f0, field, solid = _case(dims, walls, 11, solid_frac)
     force = (1e-5, -2e-5, 5e-6)
@@ -95,7 +97,7 @@ def test_adjoint_step_on_a_lattice_whose_rate_sums_take_the_two_stage_fold(stora
     lat.close()
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-13), ("f32", 1e-6)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-13), ("f32", 1e-6), ("f16", 1e-6), ("bf16", 1e-6)])
 def test_loss_seed_matches_oracle(storage, tol):
     dims, walls = (9, 8, 4), (0, 1, 0)
     g, f0, field, solid = _case(dims, walls, 21, 0.15)
@@ -116,6 +118,104 @@ def test_loss_seed_matches_oracle(storage, tol):
     got = lam.double().cpu().numpy()
     assert np.max(np.abs(got[:, fl] - lr[:, fl])) <= tol * np.max(np.abs(lr))
     assert np.max(np.abs(gF.double().cpu().numpy()[:, fl] - gFr[:, fl])) <= tol * np.max(np.abs(gFr))
+    lat.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-5)])
+def test_adjoint_step_with_moving_walls_matches_the_static_wall_adjoint(storage, tol):
+    """The momentum a moving wall adds to a bounced population is a constant, so the step's Jacobian --
+    and its adjoint -- is that of the same lattice with walls at rest, evaluated at the populations the
+    kernel reads (which include the wall's momentum)."""
+    from paper_1801_04586_amd import Lattice
+
+    dims, walls = (7, 6, 5), (1, 1, 1)
+    g, f0, field, solid = _case(dims, walls, 31, 0.1)
+    rng = np.random.default_rng(37)
+    wv = {(a, sd): tuple(0.05 * rng.standard_normal(3)) for a in range(3) for sd in (0, 1)}
+    force = (1e-5, -2e-5, 5e-6)
+    lat = Lattice(dims, walls, storage, RATES, force=force, force_field=field, solid=solid, wall_velocity=wv)
+    lat.set_populations(torch.from_numpy(f0))
+    lat.step(1)  # a state written by a step with moving walls
+    f_state = lat.populations().cpu().numpy()
+    real = lat.real
+    ln = torch.from_numpy(np.random.default_rng(5).normal(0, 1, (27,) + g.shape)).to("cuda", real).contiguous()
+    lo = torch.empty_like(ln)
+    gF = torch.zeros((3,) + g.shape, dtype=real, device="cuda")
+    gs = torch.zeros(10, dtype=torch.float64, device="cuda")
+    lat.ctx.adjoint_step(lat.state, ln, lo, gF, gs)
+    ref_lam, ref_gF, ref_gs = oracle.adjoint_step(g, f_state, ln.double().cpu().numpy(), RATES, force=force,
+                                                  force_field=lat.force_field.double().cpu().numpy(), solid=solid)
+    fl = solid == 0
+    got = lo.double().cpu().numpy()
+    assert np.max(np.abs(got[:, fl] - ref_lam[:, fl])) <= tol * np.max(np.abs(ref_lam[:, fl]))
+    assert np.max(np.abs(gF.double().cpu().numpy()[:, fl] - ref_gF[:, fl])) <= tol * np.max(np.abs(ref_gF[:, fl]))
+    gsg = gs.cpu().numpy()
+    assert np.max(np.abs(gsg[2:] - ref_gs[2:])) <= tol * np.max(np.abs(ref_gs[2:])) * 10
+    lat.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-5)])
+def test_adjoint_step_and_loss_seed_with_a_force_scale(storage, tol):
+    """clbm_set_force with a scale other than 1: the kernels use F = uniform + scale * field, so the
+    oracle is run with the scaled field; dJ/dF is the gradient with respect to that total force."""
+    dims, walls = (7, 6, 5), (0, 1, 0)
+    g, f0, field, solid = _case(dims, walls, 41, 0.1)
+    force, scale = (1e-5, -2e-5, 5e-6), -2.75
+    lat = _lattice(dims, walls, storage, force=force, field=field, solid=solid)
+    lat.set_force(force, field, scale)
+    lat.set_populations(torch.from_numpy(f0))
+    f_state = lat.populations().cpu().numpy()
+    Fs = scale * lat.force_field.double().cpu().numpy()
+    real = lat.real
+    ln = torch.from_numpy(np.random.default_rng(43).normal(0, 1, (27,) + g.shape)).to("cuda", real).contiguous()
+    lo = torch.empty_like(ln)
+    gF = torch.zeros((3,) + g.shape, dtype=real, device="cuda")
+    gs = torch.zeros(10, dtype=torch.float64, device="cuda")
+    lat.ctx.adjoint_step(lat.state, ln, lo, gF, gs)
+    ref_lam, ref_gF, ref_gs = oracle.adjoint_step(g, f_state, ln.double().cpu().numpy(), RATES, force=force,
+                                                  force_field=Fs, solid=solid)
+    fl = solid == 0
+    assert np.max(np.abs(lo.double().cpu().numpy()[:, fl] - ref_lam[:, fl])) <= tol * np.max(np.abs(ref_lam[:, fl]))
+    assert np.max(np.abs(gF.double().cpu().numpy()[:, fl] - ref_gF[:, fl])) <= tol * np.max(np.abs(ref_gF[:, fl]))
+    assert np.max(np.abs(gs.cpu().numpy()[2:] - ref_gs[2:])) <= tol * np.max(np.abs(ref_gs[2:])) * 10
+    ut = workloads.uniform_random_velocity(dims, 0.03, 44)
+    utd = torch.from_numpy(ut).to("cuda", real).contiguous()
+    lam = torch.empty((27,) + g.shape, dtype=real, device="cuda")
+    gF2 = torch.zeros((3,) + g.shape, dtype=real, device="cuda")
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lat.ctx.loss_seed(lat.state, utd, lam, gF2, J)
+    Jr, lr, gFr = oracle.loss_seed(g, f_state, utd.double().cpu().numpy(), force=force, force_field=Fs, solid=solid)
+    assert abs(J.item() - Jr) <= tol * Jr
+    assert np.max(np.abs(lam.double().cpu().numpy()[:, fl] - lr[:, fl])) <= tol * np.max(np.abs(lr))
+    assert np.max(np.abs(gF2.double().cpu().numpy()[:, fl] - gFr[:, fl])) <= tol * np.max(np.abs(gFr))
+    lat.close()
+
+
+def test_adjoint_buffers_of_the_wrong_type_or_size_are_refused():
+    """The binding checks dtype and element count of every adjoint-side buffer before the call."""
+    dims = (6, 5, 4)
+    lat = _lattice(dims, (0, 1, 0), "f16")
+    n = int(np.prod(dims))
+    lam = torch.zeros((27,) + lat.shape, dtype=torch.float32, device="cuda")
+    lam2 = torch.zeros_like(lam)
+    for bad in (lam.half(), lam.double(), torch.zeros(27 * n + 1, dtype=torch.float32, device="cuda"),
+                torch.zeros_like(lat.state, dtype=torch.float32)):
+        with pytest.raises(ValueError):
+            lat.ctx.adjoint_step(lat.state, bad, lam2)
+    with pytest.raises(ValueError):
+        lat.ctx.adjoint_step(lat.state, lam, lam2, dJds=torch.zeros(10, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        lat.ctx.adjoint_step(lat.state, lam, lam2, dJdF=torch.zeros((3, n), dtype=torch.float64, device="cuda"))
+    ut = torch.zeros((3,) + lat.shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        lat.ctx.loss_seed(lat.state, ut.double(), lam)
+    with pytest.raises(ValueError):
+        lat.ctx.loss_seed(lat.state, ut, lam, J=torch.zeros(2, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        lat.ctx.step(lat.state.float(), lat.other)  # state of another type
+    lat.ctx.adjoint_step(lat.state, lam, lam2)  # the right buffers pass
+    lat.ctx.loss_seed(lat.state, ut, lam)
+    torch.cuda.synchronize()
     lat.close()
 
 
@@ -242,3 +342,60 @@ def test_adjoint_on_full_channel_case_fp32_vs_fp64_differences():
     fd = (Jof(F32, sp) - Jof(F32, sm)) / (2 * h)
     assert abs(fd - gs[k]) <= 1e-3 * abs(fd)
     lat64.close()
+
+
+def test_flow_loss_gradient_with_a_force_scale_matches_central_differences_fp64():
+    """With force_scale != 1 the loss depends on the field through F = scale * field, so dJ/dfield is
+    scale times the adjoint's dJ/dF (central differences, FP64)."""
+    from paper_1801_04586_amd.adjoint import flow_loss
+
+    dims, T = (8, 10, 6), 30
+    lat, state0, F, ut, rates = _channel(dims, "f64")
+    lat.set_force_scale(-1.7)
+    utd = torch.from_numpy(ut).cuda()
+    Ft = torch.from_numpy(F).cuda().requires_grad_(True)
+    J = flow_loss(Ft, torch.from_numpy(rates.copy()), lat, state0, utd, T, 7)
+    J.backward()
+    gF = Ft.grad.cpu().numpy()
+
+    def Jof(Fa):
+        with torch.no_grad():
+            return flow_loss(torch.from_numpy(Fa).cuda(), torch.from_numpy(rates), lat, state0, utd, T, 7).item()
+
+    v = np.random.default_rng(13).normal(0, 1, F.shape)
+    eps = 1e-4 * np.max(np.abs(F))
+    fd = (Jof(F + eps * v) - Jof(F - eps * v)) / (2 * eps)
+    assert abs(fd - np.sum(gF * v)) <= 1e-6 * abs(fd), (fd, np.sum(gF * v))
+    lat.close()
+
+
+def test_backward_uses_the_rates_and_force_of_its_own_forward_pass():
+    """Two losses on one lattice with different rates and force scales, then one backward through both:
+    each backward must run with the rates, force and scale its forward pass used (saved with it), so the
+    sum of gradients equals the gradients taken one loss at a time."""
+    from paper_1801_04586_amd.adjoint import flow_loss
+
+    dims, T = (8, 10, 6), 20
+    lat, state0, F, ut, rates = _channel(dims, "f64")
+    utd = torch.from_numpy(ut).cuda()
+    r2 = rates.copy()
+    r2[2] *= 0.9
+    r2[4] = 1.2
+
+    def grads(pairs):
+        Ft = torch.from_numpy(F).cuda().requires_grad_(True)
+        st = torch.from_numpy(rates.copy()).requires_grad_(True)
+        total = 0.0
+        for r, scale in pairs:
+            lat.set_force_scale(scale)
+            total = total + flow_loss(Ft, st * torch.from_numpy(r / rates), lat, state0, utd, T, 6)
+        total.backward()
+        return total.item(), Ft.grad.cpu().numpy(), st.grad.numpy()
+
+    Ja, gFa, gsa = grads([(rates, 1.0)])
+    Jb, gFb, gsb = grads([(r2, 0.6)])
+    Jab, gFab, gsab = grads([(rates, 1.0), (r2, 0.6)])
+    assert abs(Jab - (Ja + Jb)) <= 1e-12 * abs(Jab)
+    assert np.max(np.abs(gFab - (gFa + gFb))) <= 1e-10 * np.max(np.abs(gFab))
+    assert np.max(np.abs(gsab - (gsa + gsb))) <= 1e-10 * np.max(np.abs(gsab))
+    lat.close()

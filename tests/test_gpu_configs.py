@@ -213,8 +213,10 @@ def test_kolmogorov_512_linear_spinup_fp32(kolmogorov_inputs):
 
 def test_kolmogorov_512_storage_errors_against_fp64_after_500_steps(kolmogorov_inputs):
     """The precision workload: velocity after 500 steps with FP32, FP16 and BF16 deviation storage
-    (FP32 arithmetic) against FP64 storage on the same inputs.  FP32 meets the 1e-5 relative target;
-    FP16 and BF16 keep the errors their 11- and 8-bit significands allow (measured 2.8e-4 and 1.9e-2)."""
+    (FP32 arithmetic) against FP64 storage on the same inputs.  The 1e-5 target for FP32 is met as an
+    L2-relative error (measured 5.9e-6); the largest nodal error relative to max |u| is 1.05e-5 and is
+    bounded separately.  FP16 and BF16 keep the errors their 11- and 8-bit significands allow (measured
+    L2 2.8e-4 and 1.86e-2, max 1.6e-3 and 4.2e-2); the bounds sit about 1.5x above the measurements."""
     cfg = workloads.KOLMOGOROV512
     u0, F = kolmogorov_inputs
     lat = _lattice(cfg.dims, cfg.walls, "f64", cfg.rates(), field=F)
@@ -225,15 +227,20 @@ def test_kolmogorov_512_storage_errors_against_fp64_after_500_steps(kolmogorov_i
     del lat
     torch.cuda.empty_cache()
     nrm = torch.linalg.vector_norm(u64)
-    for storage, tol in (("f32", 1e-5), ("f16", 1e-3), ("bf16", 5e-2)):
+    umax = u64.abs().max()
+    for storage, tol, tol_max in (("f32", 1e-5, 1.5e-5), ("f16", 4e-4, 2.5e-3), ("bf16", 2.5e-2, 6.5e-2)):
         ls = _lattice(cfg.dims, cfg.walls, storage, cfg.rates(), field=F)
         ls.init(None, u0)
         ls.step(cfg.steps)
         _, u, _, nbad = ls.moments()
         assert nbad == 0
-        err = (torch.linalg.vector_norm(u - u64) / nrm).item()
-        print(f"Kolmogorov 512^3, {storage} storage: L2-relative velocity error {err:.3e}")
+        d = u - u64
+        err = (torch.linalg.vector_norm(d) / nrm).item()
+        err_max = (d.abs().max() / umax).item()
+        print(f"Kolmogorov 512^3, {storage} storage: velocity error L2-relative {err:.3e}, max {err_max:.3e}")
         assert err < tol, (storage, err)
+        assert err_max < tol_max, (storage, err_max)
+        del d
         ls.close()
         del ls, u
         torch.cuda.empty_cache()

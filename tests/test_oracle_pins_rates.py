@@ -144,32 +144,33 @@ def _face_velocities(rng):
     return rng.uniform(-0.05, 0.05, (6, 3))
 
 
-@pytest.mark.parametrize("model", ["cascaded", "mrt"])
-def test_walls_moving_with_the_fluid_keep_a_uniform_flow(orc, model):
+@pytest.mark.parametrize("model,lattice", [("cascaded", "d3q27"), ("mrt", "d3q27"), ("cascaded", "d3q19")])
+def test_walls_moving_with_the_fluid_keep_a_uniform_flow(orc, model, lattice):
     """Bounce-back from a wall moving at u_w returns f*_i - 2 w_i (e_i . u_w)/c_s^2.  When every face moves
     with the velocity U of a uniform equilibrium at rho = 1, the correction equals f_eq,i - f_eq,opp(i) for
     the equilibria used here (U along one axis for the cascaded generalized equilibrium; any U for the
     discrete equilibrium of the MRT), so the uniform state is stationary on a box walled on every axis --
     also for links that cross two or three faces at once (edges, corners), which therefore must take
-    the velocity U, i.e. the mean of the faces they cross."""
+    the velocity U, i.e. the mean of the faces they cross.  The same holds on the D3Q19 lattice of
+    Appendix A, whose edge links cross two faces at the box's edges."""
     dims = (4, 5, 3)
     g = orc.Geometry(dims, (1, 1, 1))
     U = np.array([0.04, 0.0, 0.0]) if model == "cascaded" else np.array([0.03, -0.02, 0.025])
     u0 = np.zeros((3,) + g.shape)
     u0[:] = U[:, None, None, None]
-    f = orc.init(g, None, u0, model=model)
+    f = orc.init(g, None, u0, model=model, lattice=lattice)
     wall_u = np.tile(U, (6, 1))
     s = np.array([1.0, 1.0, 1.3, 1.1, 1.2, 0.9, 1.05, 1.15, 0.95, 1.25])
-    f5 = orc.run(g, f, s, 5, model=model, wall_velocity=wall_u)
+    f5 = orc.run(g, f, s, 5, model=model, wall_velocity=wall_u, lattice=lattice)
     assert np.max(np.abs(f5 - f)) < 1e-15, np.max(np.abs(f5 - f))
     # with the faces at rest the same state is not stationary
-    assert np.max(np.abs(orc.run(g, f, s, 1, model=model) - f)) > 1e-3
+    assert np.max(np.abs(orc.run(g, f, s, 1, model=model, lattice=lattice) - f)) > 1e-3
 
 
 def _permute_case(orc, perm, flip, dims, f, wall_u, Ff, solid):
     """Image of a lattice state under an axis permutation (new axis b = old axis perm[b]) followed by a
     reflection of the new axes with flip[b] = 1.  Returns (dims, f, wall_u, Ff, solid) of the image."""
-    e = orc.velocities()
+    e = orc.velocities() if f.shape[0] == 27 else orc.q19_velocities()
     nd = tuple(dims[perm[b]] for b in range(3))
 
     def vec_img(v):  # vector components of the image
@@ -187,10 +188,10 @@ def _permute_case(orc, perm, flip, dims, f, wall_u, Ff, solid):
 
     # population i -> population j with e_j = image of e_i
     idx = {tuple(v): j for j, v in enumerate(e)}
-    pmap = [idx[tuple(vec_img(e[i]))] for i in range(27)]
+    pmap = [idx[tuple(vec_img(e[i]))] for i in range(len(e))]
     fi = field_img(f)
     fn = np.empty_like(fi)
-    for i in range(27):
+    for i in range(len(e)):
         fn[pmap[i]] = fi[i]
     wn = np.zeros((6, 3))
     for b in range(3):
@@ -223,13 +224,14 @@ def test_moving_wall_step_commutes_with_axis_permutations_and_reflections(orc, p
     Ff = workloads.gaussian_force(dims, 1e-4, 83)
     solid = workloads.random_solids(dims, 0.1, 89)
     s = np.array([1.0, 1.0, 1.3, 1.1, 1.2, 0.9, 1.05, 1.15, 0.95, 1.25])
-    for model in ("cascaded", "mrt"):
-        out = orc.run(g, f, s, 2, force_field=Ff, solid=solid, model=model, wall_velocity=wall_u)
-        nd, fn, wn, Fn, sn = _permute_case(orc, perm, flip, dims, f, wall_u, Ff, solid)
+    f19 = orc.init(g, rho0, u0, lattice="d3q19")
+    for model, lattice, f_ in (("cascaded", "d3q27", f), ("mrt", "d3q27", f), ("cascaded", "d3q19", f19)):
+        out = orc.run(g, f_, s, 2, force_field=Ff, solid=solid, model=model, wall_velocity=wall_u, lattice=lattice)
+        nd, fn, wn, Fn, sn = _permute_case(orc, perm, flip, dims, f_, wall_u, Ff, solid)
         gn = orc.Geometry(nd, (1, 1, 1))
-        outn = orc.run(gn, fn, s, 2, force_field=Fn, solid=sn, model=model, wall_velocity=wn)
+        outn = orc.run(gn, fn, s, 2, force_field=Fn, solid=sn, model=model, wall_velocity=wn, lattice=lattice)
         _, want, _, _, _ = _permute_case(orc, perm, flip, dims, out, wall_u, Ff, solid)
-        assert np.max(np.abs(outn - want)) < 1e-14, (model, np.max(np.abs(outn - want)))
+        assert np.max(np.abs(outn - want)) < 1e-14, (model, lattice, np.max(np.abs(outn - want)))
 
 
 def _lid_duct_series(a, U, y, z, nterms=2001):
