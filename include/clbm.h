@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 5
+#define CLBM_ABI_VERSION 6
 
 /* Velocity sets: D3Q27 (Eq. (1), moment set Eq. (12)) and D3Q19 (Appendix A,
  * Eq. (A1)-(A6): velocities without the eight corners, moments of Eq. (A2),
@@ -206,6 +206,15 @@ int clbm_step(clbm_ctx *ctx, const void *src, void *dst);
  * unit (CLBM_OPT_* flags override this); otherwise every step is one
  * clbm_step.  nsteps >= 0. */
 int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result);
+
+/* nsteps steps from the state in src, keeping every state (not in the paper; for the adjoint's
+ * recomputation): states (host array of nsteps device state
+ * buffers, distinct from src and from one another) gets the state after k + 1 steps in states[k]; src
+ * is not modified.  Where
+ * clbm_run fuses pairs of steps, one launch runs two steps and also stores the state between them
+ * (read once, written twice per two steps instead of two reads and two writes); the results are
+ * bitwise those of clbm_step calls.  nsteps >= 0 (0: nothing happens). */
+int clbm_trajectory(clbm_ctx *ctx, const void *src, void *const *states, int32_t nsteps);
 
 /* Option flags (clbm_set_options). */
 #define CLBM_OPT_SINGLE_STEP 1u /* clbm_run launches one step at a time */

@@ -8,12 +8,13 @@ the hand-written adjoint kernels (``clbm_loss_seed``, ``clbm_adjoint_step``):
 
   * forward: T steps through clbm_run (fused step pairs where it uses them),
     a copy of the state kept every K steps (checkpoints);
-  * backward: segments from last to first; each segment's K states are
-    recomputed from its checkpoint by single steps (bitwise identical to the
-    original run, fused pairs being bitwise two single steps), then the
-    adjoint steps walk back through them.
+  * backward: segments from last to first; the K - 1 states after a
+    segment's checkpoint are recomputed from it by clbm_trajectory (fused
+    step pairs that also store the state between them, where clbm_run fuses;
+    bitwise identical to the original run either way), then the adjoint
+    steps walk back through the checkpoint and those states.
 
-Memory: ceil(T/K) checkpoints + K segment states + two adjoint buffers.
+Memory: ceil(T/K) checkpoints + K - 1 segment states + two adjoint buffers.
 """
 from __future__ import annotations
 
@@ -72,15 +73,14 @@ class _FlowLoss(torch.autograd.Function):
         lam2 = torch.empty_like(lam)
         dJds = torch.zeros(10, dtype=torch.float64, device=lat.device)
         nseg = len(ctx.ckpts)
-        seg = [torch.empty_like(ctx.ckpts[0]) for _ in range(min(K, max(nsteps, 1)))] if nseg else []
+        seg = [torch.empty_like(ctx.ckpts[0]) for _ in range(min(K, nsteps) - 1)] if nseg else []
         for sidx in range(nseg - 1, -1, -1):
             t0 = sidx * K
             t1 = min(t0 + K, nsteps)
-            c.copy(ctx.ckpts[sidx], seg[0])
-            for k in range(1, t1 - t0):
-                c.step(seg[k - 1], seg[k])
+            states = [ctx.ckpts[sidx]] + seg[: t1 - t0 - 1]  # states at t0 ... t1 - 1
+            c.trajectory(states[0], states[1:])
             for t in range(t1 - 1, t0 - 1, -1):
-                c.adjoint_step(seg[t - t0], lam, lam2, dJdF, dJds)
+                c.adjoint_step(states[t - t0], lam, lam2, dJdF, dJds)
                 lam, lam2 = lam2, lam
         g = gJ.to(torch.float64)
         # the kernels accumulate dJ/dF for the total force F = uniform + force_scale * field
@@ -117,4 +117,4 @@ def initial_gradient(lat: Lattice, state0: torch.Tensor, u_target: torch.Tensor,
 
 def checkpoint_memory_bytes(lat: Lattice, nsteps: int, K: int) -> int:
     per = lat.state.numel() * lat.state.element_size()
-    return (math.ceil(nsteps / K) + K) * per
+    return (math.ceil(nsteps / K) + K - 1) * per

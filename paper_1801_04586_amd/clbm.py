@@ -23,7 +23,7 @@ STORAGE_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float1
 # arithmetic / adjoint / force-field type per storage
 REAL_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float32, "bf16": torch.float32}
 RATE_NAMES = ("s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6")
-ABI_VERSION = 5  # CLBM_ABI_VERSION of include/clbm.h
+ABI_VERSION = 6  # CLBM_ABI_VERSION of include/clbm.h
 CLBM_D3Q27, CLBM_D3Q19 = 0, 1
 LATTICE = {"d3q27": CLBM_D3Q27, "d3q19": CLBM_D3Q19}
 LATTICE_Q = {"d3q27": 27, "d3q19": 19}
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "clbm_init": ([vp, vp, vp, vp], ctypes.c_int),
         "clbm_step": ([vp, vp, vp], ctypes.c_int),
         "clbm_run": ([vp, vp, vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "clbm_trajectory": ([vp, vp, ctypes.POINTER(vp), i32], ctypes.c_int),
         "clbm_set_options": ([vp, ctypes.c_uint32], ctypes.c_int),
         "clbm_fused_pairs": ([vp], ctypes.c_int),
         "clbm_copy": ([vp, vp, vp], ctypes.c_int),
@@ -188,6 +189,11 @@ class Context:
         res = ctypes.c_void_p()
         self._call("clbm_run", self._state(a), self._state(b), ctypes.c_int32(int(nsteps)), ctypes.byref(res))
         return res.value == b.data_ptr()
+
+    def trajectory(self, src, states):
+        """clbm_trajectory: states[k] gets the state after k + 1 steps from src."""
+        arr = (ctypes.c_void_p * max(len(states), 1))(*[self._state(t) for t in states])
+        self._call("clbm_trajectory", self._state(src), arr, ctypes.c_int32(len(states)))
 
     def set_options(self, options: int):
         self._call("clbm_set_options", ctypes.c_uint32(int(options)))

@@ -3,10 +3,12 @@
 // D3Q19) cascaded LBM kernels in kernels.hpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/clbm.h"
 #include "kernels.hpp"
@@ -32,7 +34,7 @@ struct clbm_ctx {
     uint32_t *links;   // [N] link table (k_links) when the lattice has solid nodes, else NULL
     uint32_t options;  // CLBM_OPT_* flags
     int num_cu;        // compute units of the device
-    int t2_slots[2][2][2];  // resident blocks of the fused kernel, by (links, force field, collision); 0 = unknown
+    int t2_slots[2][2][2][2];  // resident blocks of the fused kernel, by (links, force field, collision, keep); 0 = unknown
     char err[512];
 };
 
@@ -288,7 +290,9 @@ uint32_t fused_chunks(uint32_t tiles, uint32_t nz, uint32_t slots)
     return best;
 }
 
-int launch_step2(clbm_ctx *c, const void *src, void *dst)
+// Two steps src -> dst in one launch; with mid != NULL the state after the first step is also
+// stored there.
+int launch_step2(clbm_ctx *c, const void *src, void *dst, void *mid = nullptr)
 {
     T2Geom tg;
     tg.tiles_x = (c->geom.nx + kT2X - 1) / kT2X;
@@ -300,13 +304,14 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         using R = typename Traits<S>::R;
         constexpr bool FIELD = decltype(field_tag)::value;
         constexpr bool SOLID = decltype(solid_tag)::value;
-        auto launch = [&](auto cc) {
+        auto launch = [&](auto cc, auto keep_tag) {
             constexpr int C = decltype(cc)::value;
-            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0];
+            constexpr bool KEEP = decltype(keep_tag)::value;
+            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0][KEEP ? 1 : 0];
             if (slots == 0) {
                 int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID>, kT2Block,
-                                                                 0) != hipSuccess ||
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID, KEEP>,
+                                                                 kT2Block, 0) != hipSuccess ||
                     per_cu < 1)
                     per_cu = 1;
                 slots = per_cu * c->num_cu;
@@ -315,13 +320,17 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
             tg.zchunk = (c->geom.nz + nchunks_req - 1) / nchunks_req;
             const uint32_t nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
             const unsigned blocks = tiles * nchunks;
-            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID>), dim3(blocks), dim3(kT2Block), 0, c->stream,
-                               static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg, c->links,
-                               static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
+            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID, KEEP>), dim3(blocks), dim3(kT2Block), 0, c->stream,
+                               static_cast<const S *>(src), static_cast<S *>(dst), static_cast<S *>(mid), c->geom,
+                               tg, c->links, static_cast<const R *>(c->d.force), make_forcing<R>(c->d),
+                               make_rates<R>(c->d.s));
             return check_launch(c, "fused two-step kernel launch");
         };
-        if (coll == kCascadedHigh1) return launch(std::integral_constant<int, kCascadedHigh1>{});
-        return launch(std::integral_constant<int, kCascaded>{});
+        auto keep = [&](auto cc) {
+            return mid ? launch(cc, std::true_type{}) : launch(cc, std::false_type{});
+        };
+        if (coll == kCascadedHigh1) return keep(std::integral_constant<int, kCascadedHigh1>{});
+        return keep(std::integral_constant<int, kCascaded>{});
     };
     if (c->links)
         return c->d.force != nullptr ? go(float{}, std::true_type{}, std::true_type{})
@@ -412,9 +421,7 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
             hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             c->num_cu = 0;
         if (c->num_cu <= 0) c->num_cu = 256;
-        for (auto &plane : c->t2_slots)
-            for (auto &row : plane)
-                for (int &v : row) v = 0;
+        std::memset(c->t2_slots, 0, sizeof(c->t2_slots));
     }
     // the link table: for solid nodes, and for walls on lattices that take the fused kernel
     const bool walls = desc->wall[0] || desc->wall[1] || desc->wall[2];
@@ -540,6 +547,40 @@ int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result)
         nxt = t;
     }
     if (result) *result = cur;
+    return CLBM_OK;
+}
+
+int clbm_trajectory(clbm_ctx *ctx, const void *src, void *const *states, int32_t nsteps)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(ctx, CLBM_EINVAL, "nsteps < 0");
+    if (!src || !aligned(src)) return fail(ctx, CLBM_EINVAL, "src NULL or misaligned");
+    if (nsteps == 0) return CLBM_OK;
+    if (!states) return fail(ctx, CLBM_EINVAL, "states is NULL");
+    // every buffer distinct: a launch reads one of them while writing one or two others
+    std::vector<uintptr_t> seen;
+    seen.reserve(static_cast<size_t>(nsteps) + 1);
+    seen.push_back(reinterpret_cast<uintptr_t>(src));
+    for (int32_t k = 0; k < nsteps; ++k) {
+        if (!states[k] || !aligned(states[k])) return fail(ctx, CLBM_EINVAL, "a state buffer is NULL or misaligned");
+        seen.push_back(reinterpret_cast<uintptr_t>(states[k]));
+    }
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+        return fail(ctx, CLBM_EINVAL, "src and the state buffers must be distinct");
+    const void *cur = src;
+    int32_t k = 0;
+    if (fused_pairs(ctx))
+        for (; k + 2 <= nsteps; k += 2) {
+            const int rc = launch_step2(ctx, cur, states[k + 1], states[k]);
+            if (rc) return rc;
+            cur = states[k + 1];
+        }
+    for (; k < nsteps; ++k) {
+        const int rc = launch_step(ctx, cur, states[k]);
+        if (rc) return rc;
+        cur = states[k];
+    }
     return CLBM_OK;
 }
 

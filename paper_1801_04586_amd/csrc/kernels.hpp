@@ -535,12 +535,14 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
     return static_cast<uint32_t>(r < 0 ? r + static_cast<int>(n) : r);
 }
 
+// KEEP: also store the intermediate state (after step t+1) into `mid`, as a single step would have
+// written it; each tile stores its own nodes of its own planes, so every node is written once.
 // (the waves-per-EU bound keeps the register budget at or below 128)
-template <typename S, bool FIELD, int COLL, bool SOLID>
+template <typename S, bool FIELD, int COLL, bool SOLID, bool KEEP>
 __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) void k_step2(
-    const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const uint32_t *__restrict__ links,
-    const typename Traits<S>::R *__restrict__ field, Forcing<typename Traits<S>::R> fo,
-    Rates<typename Traits<S>::R> rt)
+    const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ mid, Geom g, T2Geom tg,
+    const uint32_t *__restrict__ links, const typename Traits<S>::R *__restrict__ field,
+    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
 {
     using R = typename Traits<S>::R;
     static_assert(std::is_same<R, float>::value, "the LDS ring holds FP32 values");
@@ -584,6 +586,9 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     const int hs = hy * kT2HX + hx;
     const bool ha = tid < kT2H;
     const uint32_t gx = wrap_coord(x0 - 1 + hx, g.nx), gy = wrap_coord(y0 - 1 + hy, g.ny);
+    // KEEP: this thread's first-step node belongs to the tile (not to its halo ring) and to the lattice
+    const bool own = hx >= 1 && hx <= kT2X && hy >= 1 && hy <= kT2Y && x0 - 1 + hx < static_cast<int>(g.nx) &&
+                     y0 - 1 + hy < static_cast<int>(g.ny);
     const int cx = tid % kT2X, cy = tid / kT2X;
     const bool ca = tid < kT2X * kT2Y && x0 + cx < static_cast<int>(g.nx) && y0 + cy < static_cast<int>(g.ny);
 
@@ -619,6 +624,15 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
         node_update<COLL>(v, Fx, Fy, Fz, rt);
+        if constexpr (KEEP) {
+            if (own && p >= z0 && p < z1) {
+                const uint32_t off = n * static_cast<uint32_t>(sizeof(S));
+                sfor<0, 27>([&](auto TT) {
+                    constexpr int t = decltype(TT)::value;
+                    store_at(mid + static_cast<size_t>(pop_of_slot(t)) * g.P, off, to_store<S>(v[t]));
+                });
+            }
+        }
         const int r0 = zm(p);
         sfor<0, 9>([&](auto J) {
             constexpr int j = decltype(J)::value;  // j = 3 a + b; slot 3 j + c with c = e_z + 1
@@ -953,8 +967,10 @@ __device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const
 {
     using R = typename Traits<S>::R;
     constexpr R cs2 = R(1.0 / 3.0), cs4 = R(1.0 / 9.0);
-    double gs[kAdjRates] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    // this node's dJ/ds terms, summed over its moments in the arithmetic type; the sums over nodes are FP64
+    R gsr[kAdjRates] = {};
+    // XCD-aware order, as the step kernels: the +e shifted gathers of neighbouring blocks then share an L2
+    const uint32_t n = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (n < g.N) {
         // A solid node reads no state or adjoint: with zero inputs every output below is
         // exactly zero (lambda = 0, no force or rate contribution), and its stores keep
@@ -1071,7 +1087,7 @@ __device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const
                     else if constexpr (nn == 1) Fby += gF;
                     else Fbz += gF;
                 }
-                gs[k - 2] += static_cast<double>(y * r);
+                gsr[k - 2] = fma(y, r, gsr[k - 2]);
                 if constexpr (ones == 0) rhob = fma(rt.s[k] * E, y, rhob);
                 a[t] = fma(-rt.s[k], y, y);
             }
@@ -1085,9 +1101,9 @@ __device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const
             a[iy] = yy - sy;
             a[iz] = yz - sz;
             rhob = fma(cs2, sx + sy + sz, rhob);
-            const double third = static_cast<double>(ysum * rsum) / 3.0;
-            gs[R_S2 - 2] += static_cast<double>(yx * rx + yy * ry + yz * rz) - third;
-            gs[R_S2B - 2] += third;
+            const R third = ysum * rsum * R(1.0 / 3.0);
+            gsr[R_S2 - 2] += fma(yx, rx, fma(yy, ry, yz * rz)) - third;
+            gsr[R_S2B - 2] += third;
         }
         // u-derivative of N(u), then back through N(u) and M
         ubx -= lowered_dot<0>(a, tt);
@@ -1116,6 +1132,9 @@ __device__ __forceinline__ void adjoint_nodes(const S *__restrict__ state, const
             dJdF[2 * static_cast<size_t>(g.N) + n] = gFz + Fbz;
         }
     }
+    double gs[kAdjRates];
+#pragma unroll
+    for (int k = 0; k < kAdjRates; ++k) gs[k] = static_cast<double>(gsr[k]);
     block_reduce_store<kAdjRates>(gs, partials + static_cast<size_t>(blockIdx.x) * kAdjRates);
 }
 

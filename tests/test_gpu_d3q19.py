@@ -138,7 +138,7 @@ def test_adjoint_is_refused_for_d3q19():
     dims = (6, 5, 4)
     lat = _lattice(dims, (0, 0, 0), "f32")
     lat.init()
-    lam = torch.zeros((19,) + lat.shape, dtype=torch.float32, device="cuda")
+    lam = torch.zeros((27,) + lat.shape, dtype=torch.float32, device="cuda")  # adjoint buffers are [27][N]
     out = torch.empty_like(lam)
     with pytest.raises(ClbmError) as e:
         lat.ctx.adjoint_step(lat.state, lam, out)

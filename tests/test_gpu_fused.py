@@ -278,3 +278,57 @@ def test_fused_launch_writes_every_fluid_entry_and_no_padding(dims, walls, frac)
     assert np.isfinite(body[:, fl]).all()
     assert torch.isnan(out[:, n:]).all()
     lat.close()
+
+
+# ----------------------------------------------------------------------------- clbm_trajectory
+@pytest.mark.parametrize("case", ["periodic", "walls_solids", "moving_walls", "general_rates", "fp64"])
+def test_trajectory_keeps_every_state_bitwise(case):
+    """clbm_trajectory stores the state after every step; where the lattice takes fused pairs, each
+    launch also stores the state between its two steps.  Every kept state is bitwise the one single
+    steps produce, for odd and even step counts, and the source state is left untouched."""
+    from paper_1801_04586_amd import Lattice
+
+    dims = (37, 26, 18)
+    walls, solid, wv, rates, storage = (0, 0, 0), None, None, RATES_H1, "f32"
+    if case == "walls_solids":
+        walls, solid = (0, 1, 1), workloads.random_solids(dims, 0.15, 21)
+    elif case == "moving_walls":
+        walls, wv = (1, 1, 1), {(1, 1): (0.02, 0.0, -0.01), (2, 0): (0.0, 0.015, 0.0)}
+    elif case == "general_rates":
+        rates = RATES
+    elif case == "fp64":
+        storage = "f64"
+    g, f0 = _start(dims, 23)
+    field = workloads.gaussian_force(dims, 1e-4, 24)
+    for fused in (True, False):
+        lat = Lattice(dims, walls, storage, rates, force=(1e-5, 0, 0), force_field=field, solid=solid,
+                      wall_velocity=wv)
+        lat.set_fused_steps(fused)
+        assert lat.uses_fused_pairs == (fused and storage == "f32")
+        lat.set_populations(torch.from_numpy(f0))
+        src = lat.state.clone()
+        for n in (5, 4):
+            states = [lat.new_state() for _ in range(n)]
+            lat.ctx.trajectory(src, states)
+            a, b = src.clone(), lat.new_state()
+            for k in range(n):
+                lat.ctx.step(a, b)
+                assert torch.equal(states[k], b), (case, fused, n, k)
+                a, b = b, a
+        assert torch.equal(src, lat.state)
+        lat.close()
+
+
+def test_trajectory_refuses_shared_buffers():
+    from paper_1801_04586_amd import ClbmError, Lattice
+
+    lat = Lattice((8, 8, 8), (0, 0, 0), "f32", RATES)
+    lat.init()
+    s1, s2 = lat.new_state(), lat.new_state()
+    for states in ([s1, s1], [s1, lat.state], [s1, s2, s1]):
+        with pytest.raises(ClbmError):
+            lat.ctx.trajectory(lat.state, states)
+    lat.ctx.trajectory(lat.state, [])  # nothing to do
+    lat.ctx.trajectory(lat.state, [s1, s2])
+    torch.cuda.synchronize()
+    lat.close()
