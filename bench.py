@@ -10,15 +10,23 @@ collide-and-stream kernel); the metric is MLUPS (million lattice-node updates
 per second) and the fraction of the HBM roofline.  Inputs are resident in HBM
 before the timed region.
 
-Also reported from the same run (each timed with HIP events, trimmed mean of
-9 repetitions as in the paper's Table I protocol): the single-step kernel and
-dense planes on the same lattice; FP64, FP16 and BF16 storage; the MRT of
-Appendix B and the D3Q19 scheme of Appendix A; the lid-driven cavity 256^3;
-Table I's shear-wave workload (cascaded against SRT, also from HIP graph
-replays); the 128^3 Taylor-Green case; the porous duct 640x320x320; the
-adjoint step and the end-to-end gradient on its 256x128x128 crop and on the
-64^3 channel; the velocity error of every storage type against FP64 after
-500 steps; and the FP64 CPU oracle on bounded samples.
+Also reported from the same run (each timed with HIP events on the stream the
+kernels run on, trimmed mean of 9 repetitions as in the paper's Table I
+protocol) -- the variants below, by name; `--only NAME[,NAME...]` runs just
+those (one lattice per process, for profilers):
+  kolmogorov_512_f32_single, kolmogorov_512_f32_dense   single steps; dense planes
+  kolmogorov_512_{f64,f16,bf16}                          other storage types
+  kolmogorov_512_general_f32                             non-slip s3 and s2b = s2 (general collision)
+  kolmogorov_512_mrt_f32, kolmogorov_512_d3q19_{f32,f64,f16}   Appendix B and Appendix A
+  cavity_256_{cascaded,mrt}_f32                          lid-driven cavity, all walls
+  table_I_latency, table_I_bandwidth                     Table I's cascaded/SRT cost ratio
+  taylor_green_128_{f64,f32}
+  porous_640x320x320_f32, porous_640x320x320_general_f32
+  adjoint_channel_64_f32                                 end-to-end gradient, T = 200, K = 20
+  adjoint_porous_256x128x128_f32                         adjoint step, recompute, backward, gradient
+  adjoint_porous_640x320x320_f32                         adjoint step and recompute on the full duct
+plus the velocity error of every storage type against FP64 after 500 steps,
+and the FP64 CPU oracle on bounded samples.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -28,6 +36,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -39,6 +48,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD datasheet
 PMC_SINGLE = os.path.join(ROOT, "profiles", "pmc_k_step_f32_kolmogorov512.json")
 PMC_FUSED = os.path.join(ROOT, "profiles", "pmc_k_step2_f32_kolmogorov512.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_04586_amd", "csrc", f) for f in ("node.hpp", "kernels.hpp")]
+HEADLINE = "kolmogorov_512_f32"
+# bytes per node of one adjoint step: state 27 x 4, lambda in and out 2 x 27 x 4, dJ/dF read and written
+# 2 x 3 x 4, force field 3 x 4, solid mask 1; counted over all nodes (the kernel reads and writes whole
+# lines, solid nodes included), as "frac"; "frac_fluid" counts fluid nodes only
+ADJ_BYTES = 27 * 4 * 3 + 24 + 12 + 1
 
 
 def log(*a):
@@ -82,85 +96,468 @@ def trimmed_mean(xs):
     return sum(xs) / len(xs)
 
 
-def time_steps(torch, lat, steps, reps=9):
-    """Trimmed-mean ms per step over `reps` repetitions of `steps` steps (HIP events)."""
-    out = []
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        lat.step(steps)
-        b.record()
-        b.synchronize()
-        out.append(a.elapsed_time(b) / steps)
-    return trimmed_mean(out)
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
-def graph_of_steps(torch, lat, steps):
-    """A HIP graph (torch.cuda.CUDAGraph) of lat.step(steps), captured on a side stream.  With an even
-    number of launches the state ends in the buffer it started in, so every replay advances it."""
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(graph, stream=side):
-            lat.step(steps)
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    return graph
+class Bench:
+    """Shared inputs and timing helpers of one bench.py process."""
+
+    def __init__(self, args):
+        import numpy as np
+        import torch
+
+        import workloads
+
+        self.args, self.np, self.torch, self.workloads = args, np, torch, workloads
+        self.dev = torch.device("cuda:0")
+        torch.cuda.set_device(self.dev)
+        self.L = args.size
+        self.dims = (self.L,) * 3
+        self.nodes = self.L ** 3
+        self._kolm = None
+
+    # ---- timing (HIP events on torch's current stream, where the library enqueues its kernels)
+    def ms(self, fn, per: int, reps: int = 9) -> float:
+        """Trimmed-mean milliseconds per unit over `reps` repetitions of fn(), which does `per` units."""
+        torch = self.torch
+        out = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            out.append(a.elapsed_time(b) / per)
+        return trimmed_mean(out)
+
+    def step_ms(self, lat, steps: int = 10, reps: int = 9) -> float:
+        return self.ms(lambda: lat.step(steps), steps, reps)
+
+    def record(self, nodes: int, ms: float, bpn: float, **extra):
+        return {"mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                "bytes_per_node": round(bpn, 2), "frac": round(bpn * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                **extra}
+
+    # ---- inputs
+    def kolmogorov(self):
+        """(u0 device FP64, F device FP32, F numpy) of the 512^3 workload, generated once."""
+        if self._kolm is None:
+            u0 = self.workloads.uniform_random_velocity(self.dims, 1e-3, self.workloads.SEED)
+            F = self.workloads.kolmogorov_force(self.dims, 1e-5, 4)
+            self._kolm = (self.torch.from_numpy(u0).to(self.dev), self.torch.from_numpy(F).to(self.dev, self.torch.float32),
+                          F, u0)
+        return self._kolm
+
+    def kolmogorov_lattice(self, storage="f32", rates=None, **kw):
+        from paper_1801_04586_amd import Lattice
+
+        u0d, F32, F, _ = self.kolmogorov()
+        field = self.torch.from_numpy(F).to(self.dev) if storage == "f64" else F32
+        r = self.workloads.rates(0.005) if rates is None else rates
+        lat = Lattice(self.dims, (0, 0, 0), storage, r, force_field=field, device=self.dev, **kw)
+        lat.init(None, u0d)
+        return lat
+
+    def done(self, *lats):
+        for lat in lats:
+            lat.close()
+        self.torch.cuda.empty_cache()
 
 
-def kolmogorov_inputs(dims):
-    import workloads
+def nonslip_rates(workloads, nu):
+    """The walled setting of Sec. III B: non-slip s3 = (16 - 8 s2)/(8 - s2) and s2b = s2, so the general
+    collision runs (rates above second order are not all 1)."""
+    s2 = workloads.s2_from_nu(nu)
+    return workloads.rates(nu, s2b=s2, s3=workloads.nonslip_s3(s2))
 
-    u0 = workloads.uniform_random_velocity(dims, 1e-3, workloads.SEED)
-    F = workloads.kolmogorov_force(dims, 1e-5, 4)
-    return u0, F
+
+# ------------------------------------------------------------------------------------------------ variants
+def v_kolmogorov_single(b: Bench):
+    lat = b.kolmogorov_lattice()
+    lat.set_fused_steps(False)
+    lat.step(2)
+    r = b.record(b.nodes, b.step_ms(lat), bytes_per_node("f32", True, False), launch="one step",
+                 traffic=pmc_traffic(PMC_SINGLE, b.L, False))
+    b.done(lat)
+    return r
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--size", type=int, default=512, help="edge of the cubic Kolmogorov lattice")
-    ap.add_argument("--primary-only", action="store_true", help="time only the FP32 step (for profilers)")
-    ap.add_argument("--copy-calibration", action="store_true", help="also run the plain copy kernel (PMC scale)")
-    ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    args = ap.parse_args()
+def v_kolmogorov_dense(b: Bench):
+    lat = b.kolmogorov_lattice(plane_stride=0)
+    lat.step(4)
+    bpn = bytes_per_node("f32", True, False)
+    r = b.record(b.nodes, b.step_ms(lat), bpn, launch="two fused steps", plane_stride=lat.P)
+    lat.set_fused_steps(False)
+    r["single_step"] = b.record(b.nodes, b.step_ms(lat), bpn)
+    b.done(lat)
+    return r
 
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
-              file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
-    import torch
+def v_kolmogorov_storage(storage):
+    def run(b: Bench):
+        lat = b.kolmogorov_lattice(storage)
+        lat.step(3)
+        r = b.record(b.nodes, b.step_ms(lat), bytes_per_node(storage, True, False),
+                     launch="two fused steps" if lat.uses_fused_pairs else "one step")
+        b.done(lat)
+        return r
+    return run
 
-    import workloads
+
+def v_kolmogorov_general(b: Bench):
+    """The headline lattice with the general collision (non-slip s3, s2b = s2): fused pairs and single
+    steps, and the ratio of its time to the rates-one path's."""
+    bpn = bytes_per_node("f32", True, False)
+    out = {}
+    for name, rates in (("general", nonslip_rates(b.workloads, 0.005)), ("rates_one", b.workloads.rates(0.005))):
+        lat = b.kolmogorov_lattice("f32", rates)
+        lat.step(4)
+        fused = b.step_ms(lat)
+        lat.set_fused_steps(False)
+        single = b.step_ms(lat)
+        out[name] = (fused, single)
+        b.done(lat)
+    g, one = out["general"], out["rates_one"]
+    r = b.record(b.nodes, g[0], bpn, launch="two fused steps", rates="s3 = (16 - 8 s2)/(8 - s2), s2b = s2")
+    r["single_step"] = b.record(b.nodes, g[1], bpn)
+    r["time_over_rates_one"] = {"fused": round(g[0] / one[0], 3), "single_step": round(g[1] / one[1], 3)}
+    return r
+
+
+def v_kolmogorov_mrt(b: Bench):
+    lat = b.kolmogorov_lattice("f32", collision="mrt")
+    lat.step(4)
+    r = b.record(b.nodes, b.step_ms(lat), bytes_per_node("f32", True, False), launch="one step")
+    b.done(lat)
+    return r
+
+
+def v_kolmogorov_d3q19(storage):
+    def run(b: Bench):
+        lat = b.kolmogorov_lattice(storage, lattice="d3q19")
+        lat.step(3)
+        r = b.record(b.nodes, b.step_ms(lat), bytes_per_node(storage, True, False, q=19), launch="one step")
+        b.done(lat)
+        return r
+    return run
+
+
+def v_cavity(collision):
+    def run(b: Bench):
+        from paper_1801_04586_amd import Lattice
+
+        cdims = (256, 256, 256)
+        n = 256 ** 3
+        lat = Lattice(cdims, (1, 1, 1), "f32", b.workloads.rates(0.1 * 256 / 400.0), device=b.dev,
+                      collision=collision, wall_velocity={(1, 1): (0.1, 0.0, 0.0)})
+        lat.init()
+        lat.step(3)
+        bpn = bytes_per_node("f32", False, False)
+        r = b.record(n, b.step_ms(lat), bpn, launch="two fused steps" if lat.uses_fused_pairs else "one step")
+        if lat.uses_fused_pairs:
+            lat.set_fused_steps(False)
+            r["single_step"] = b.record(n, b.step_ms(lat), bpn)
+        b.done(lat)
+        return r
+    return run
+
+
+def _shear_wave(b: Bench, dims, coll, storage, rates):
+    """Table I's workload: u = (A sin(2 pi y / ny), B, 0), A = 1e-3, B = 0.3 c_s, no force."""
     from paper_1801_04586_amd import Lattice
 
-    if not torch.cuda.is_available():
-        log("no GPU visible")
-        sys.exit(1)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    L = args.size
-    dims = (L, L, L)
-    nodes = L ** 3
-    nu = 0.005
-    rates = workloads.rates(nu)
-    log(f"[bench] Kolmogorov {dims}, nu={nu}, s2={rates[2]:.6f}; generating inputs")
-    u0, F = kolmogorov_inputs(dims)
-    u0_dev = torch.from_numpy(u0).to(dev)
-    F32_dev = torch.from_numpy(F).to(dev, torch.float32)
-    F64_dev = None
+    np = b.np
+    nx, ny, nz = dims
+    us = np.zeros((3, nz, ny, nx))
+    us[0] = (1e-3 * np.sin(2 * np.pi * np.arange(ny) / ny))[None, :, None]
+    us[1] = 0.3 / np.sqrt(3.0)
+    lat = Lattice(dims, (0, 0, 0), storage, rates, device=b.dev, collision=coll)
+    lat.init(None, us)
+    return lat
 
-    # ------------------------------------------------------------------ primary: FP32 storage
-    lat = Lattice(dims, (0, 0, 0), "f32", rates, force_field=F32_dev, device=dev)
-    lat.init(None, u0_dev)
+
+def v_table_I_latency(b: Bench):
+    """Table I's lattices (5 x ny x 5, 10 000 steps, FP64): cascaded (nu = 0.05, higher rates 1) against
+    the SRT-LBM with the discrete equilibrium, run as the MRT with every rate equal.  A step here is
+    one kernel of about 5 us, so these ratios measure launch latency, not collision cost."""
+    torch, np = b.torch, b.np
+    table = {}
+    for ny in (101, 201, 401):
+        row = {}
+        for name, coll, r in (("t_C", "cascaded", b.workloads.rates(0.05)),
+                              ("t_S", "mrt", np.full(10, b.workloads.s2_from_nu(0.05)))):
+            lat = _shear_wave(b, (5, ny, 5), coll, "f64", r)
+            lat.step(100)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat.step(10000)
+            torch.cuda.synchronize()
+            row[name] = round(time.perf_counter() - t0, 5)
+            lat.close()
+        row["t_C/t_S"] = round(row["t_C"] / row["t_S"], 3)
+        table[f"5x{ny}x5"] = row
+    return table
+
+
+def v_table_I_bandwidth(b: Bench):
+    """Table I's question where the GPU is full: the same shear wave and rates on a 512^3 lattice.  The
+    cascaded scheme and the SRT run with the same launch structure (single steps) in FP64 and in FP32
+    storage; the FP32 cascaded scheme also with its fused pairs (the SRT has no fused kernel)."""
+    np = b.np
+    dims = (512, 512, 512)
+    out = {}
+    for storage in ("f64", "f32"):
+        row = {}
+        for name, coll, r in (("t_C", "cascaded", b.workloads.rates(0.05)),
+                              ("t_S", "mrt", np.full(10, b.workloads.s2_from_nu(0.05)))):
+            lat = _shear_wave(b, dims, coll, storage, r)
+            lat.set_fused_steps(False)
+            lat.step(2)
+            row[name + "_ms_per_step"] = round(b.step_ms(lat), 4)
+            if coll == "cascaded" and storage == "f32":
+                lat.set_fused_steps(None)
+                lat.step(2)
+                row["t_C_fused_ms_per_step"] = round(b.step_ms(lat), 4)
+            b.done(lat)
+        row["t_C/t_S"] = round(row["t_C_ms_per_step"] / row["t_S_ms_per_step"], 3)
+        if "t_C_fused_ms_per_step" in row:
+            row["t_C_fused/t_S"] = round(row["t_C_fused_ms_per_step"] / row["t_S_ms_per_step"], 3)
+        row["mlups_C"] = round(b.nodes / (row["t_C_ms_per_step"] * 1e-3) / 1e6, 1)
+        row["mlups_S"] = round(b.nodes / (row["t_S_ms_per_step"] * 1e-3) / 1e6, 1)
+        out[storage] = row
+    out["workload"] = "shear wave, 512^3 periodic, nu = 0.05, Ma = 0.3, no force"
+    return out
+
+
+def v_taylor_green(storage):
+    def run(b: Bench):
+        from paper_1801_04586_amd import Lattice
+
+        tdims = (128, 128, 128)
+        rho_t, u_t = b.workloads.taylor_green_3d(tdims, 0.04)
+        lat = Lattice(tdims, (0, 0, 0), storage, b.workloads.rates(0.01), device=b.dev)
+        lat.init(rho_t, u_t)
+        lat.step(3)
+        r = b.record(128 ** 3, b.step_ms(lat, 50), bytes_per_node(storage, False, False),
+                     launch="two fused steps" if lat.uses_fused_pairs else "one step",
+                     note="2 x 226-453 MB working set: partly served by the 256 MB last-level cache")
+        b.done(lat)
+        return r
+    return run
+
+
+_POROUS = {}
+
+
+def porous_mask(b: Bench, dims):
+    if dims not in _POROUS:
+        _POROUS[dims] = b.workloads.porous_spheres(dims, (0, 1, 1), 6.0, 12.0, 0.2, b.workloads.SEED)[0]
+    return _POROUS[dims]
+
+
+def v_porous(general):
+    def run(b: Bench):
+        from paper_1801_04586_amd import Lattice
+
+        np = b.np
+        pdims = (640, 320, 320)
+        mask = porous_mask(b, pdims)
+        rates = nonslip_rates(b.workloads, 0.02) if general else b.workloads.rates(0.02)
+        lat = Lattice(pdims, (0, 1, 1), "f32", rates, force=(2e-6, 0, 0), solid=mask, device=b.dev)
+        lat.init()
+        lat.step(3)
+        pn = int(np.prod(pdims))
+        fluid = int((mask == 0).sum())
+        bpn = (2 * 27 * 4 * fluid + pn) / pn  # populations of fluid nodes + the solid mask
+        ms = b.step_ms(lat)
+        r = b.record(pn, ms, bpn, mflups_fluid=round(fluid / (ms * 1e-3) / 1e6, 1),
+                     launch="two fused steps" if lat.uses_fused_pairs else "one step",
+                     solid_fraction=round(1 - fluid / pn, 4))
+        if general:
+            r["rates"] = "s3 = (16 - 8 s2)/(8 - s2), s2b = s2"
+        if lat.uses_fused_pairs:
+            lat.set_fused_steps(False)
+            r["single_step"] = b.record(pn, b.step_ms(lat), bpn)
+        b.done(lat)
+        return r
+    return run
+
+
+def v_adjoint_channel(b: Bench):
+    """End-to-end gradient of the adjoint channel case: 64^3, T = 200, checkpoint every 20, FP32."""
+    from paper_1801_04586_amd import Lattice
+    from paper_1801_04586_amd.adjoint import flow_loss
+
+    torch, np, wl = b.torch, b.np, b.workloads
+    cdims, T, K = (64, 64, 64), 200, 20
+    Fc = wl.gaussian_force(cdims, 1e-6, wl.SEED)
+    lat = Lattice(cdims, (0, 1, 0), "f32", wl.rates(0.05), force_field=Fc, device=b.dev)
+    lat.init()
+    s0 = lat.state.clone()
+    utc = torch.from_numpy(wl.channel_target(cdims, (0, 1, 0), 1e-4)).to(b.dev, torch.float32)
+    Ft = torch.from_numpy(Fc).to(b.dev, torch.float32)
+    st = torch.from_numpy(wl.rates(0.05))
+    times = []
+    for _ in range(3):
+        Fr, sr = Ft.clone().requires_grad_(True), st.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        flow_loss(Fr, sr, lat, s0, utc, T, K).backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    cn = int(np.prod(cdims))
+    tbest = min(times)
+    b.done(lat)
+    return {"gradient_seconds": round(tbest, 4), "node_updates_per_s_M": round(cn * T * 3 / tbest / 1e6, 1),
+            "note": "forward T steps + recompute T steps + T adjoint steps, 64^3 (cache-resident, launch-bound)"}
+
+
+def _adjoint_lattice(b: Bench, adims):
+    from paper_1801_04586_amd import Lattice
+
+    wl = b.workloads
+    mask = porous_mask(b, adims)
+    Fa = wl.gaussian_force(adims, 1e-6, wl.SEED)
+    lat = Lattice(adims, (0, 1, 1), "f32", wl.rates(0.02), force=(2e-6, 0, 0), force_field=Fa, solid=mask,
+                  device=b.dev)
+    lat.init()
+    lat.step(5)
+    return lat, mask, Fa
+
+
+def _adjoint_step_and_recompute(b: Bench, lat, K: int, keep: int):
+    """Times of one adjoint step and of the recompute per step (clbm_trajectory keeping `keep` states, as
+    the gradient recomputes a segment), in ms; and of one backward segment (recompute of K - 1 states
+    plus K adjoint steps)."""
+    torch = b.torch
+    shape = lat.shape
+    ut = torch.zeros((3,) + shape, dtype=torch.float32, device=b.dev)
+    lam = torch.empty((27,) + shape, dtype=torch.float32, device=b.dev)
+    lam2 = torch.empty_like(lam)
+    gF = torch.zeros((3,) + shape, dtype=torch.float32, device=b.dev)
+    gs = torch.zeros(10, dtype=torch.float64, device=b.dev)
+    lat.ctx.loss_seed(lat.state, ut, lam, gF, None)
+    bufs = [lam, lam2]
+
+    def adj10():
+        for _ in range(5):
+            lat.ctx.adjoint_step(lat.state, bufs[0], bufs[1], gF, gs)
+            lat.ctx.adjoint_step(lat.state, bufs[1], bufs[0], gF, gs)
+
+    adj10()
+    adj_ms = b.ms(adj10, 10)
+    states = [lat.new_state() for _ in range(keep)]
+    lat.ctx.trajectory(lat.state, states)
+    traj_ms = b.ms(lambda: lat.ctx.trajectory(lat.state, states), keep, reps=5)
+    seg_ms = None
+    if keep == K - 1:
+        seg = [lat.state] + states
+
+        def segment():
+            lat.ctx.trajectory(seg[0], seg[1:])
+            for t in range(K - 1, -1, -1):
+                lat.ctx.adjoint_step(seg[t], bufs[t % 2], bufs[1 - t % 2], gF, gs)
+
+        segment()
+        seg_ms = b.ms(segment, 1, reps=5)
+    del states
+    return adj_ms, traj_ms, seg_ms
+
+
+def v_adjoint_porous_crop(b: Bench):
+    """Adjoint step on the 256x128x128 crop of the porous duct (FP32, walls in y and z, spheres, per-node
+    force field), the recompute the gradient runs (fused pairs that keep both states), one backward
+    segment of K = 20, and the gradient of the flow loss end to end (T = 40, K = 20)."""
+    from paper_1801_04586_amd.adjoint import flow_loss
+
+    torch, np, wl = b.torch, b.np, b.workloads
+    adims, K = (256, 128, 128), 20
+    lat, mask, Fa = _adjoint_lattice(b, adims)
+    an = int(np.prod(adims))
+    adj_ms, traj_ms, seg_ms = _adjoint_step_and_recompute(b, lat, K, K - 1)
+    fwd_bpn = bytes_per_node("f32", True, True)
+    fl = float((mask == 0).mean())
+    r = {"adjoint": b.record(an, adj_ms, ADJ_BYTES, frac_fluid=round(fl * ADJ_BYTES * an / (adj_ms * 1e-3) / 1e9
+                                                                       / HBM_PEAK_GBS, 4)),
+         "recompute": b.record(an, traj_ms, fwd_bpn, launch="clbm_trajectory (single steps)"),
+         "backward_segment_K20": {"ms": round(seg_ms, 4), "adjoint_steps_per_s_M": round(an * K / (seg_ms * 1e-3) / 1e6, 1),
+                                  "note": "recompute of 19 states + 20 adjoint steps, as the gradient runs it"},
+         "solid_fraction": round(float(mask.mean()), 4)}
+    Ta, Ka = 40, 20
+    s0a = lat.state.clone()
+    ut = torch.zeros((3,) + lat.shape, dtype=torch.float32, device=b.dev)
+    Fta = torch.from_numpy(Fa).to(b.dev, torch.float32)
+    sta = torch.from_numpy(wl.rates(0.02))
+    times = []
+    for _ in range(3):
+        Fr, sr = Fta.clone().requires_grad_(True), sta.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        flow_loss(Fr, sr, lat, s0a, ut, Ta, Ka).backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    tg = min(times)
+    r["gradient_T40_K20"] = {"seconds": round(tg, 4),
+                             "node_updates_per_s_M": round(an * Ta * 3 / tg / 1e6, 1),
+                             "note": "forward 40 steps + recompute + 40 adjoint steps"}
+    b.done(lat)
+    return r
+
+
+def v_adjoint_porous_full(b: Bench):
+    """The adjoint step and its recompute on the full 640x320x320 porous duct."""
+    np = b.np
+    adims = (640, 320, 320)
+    lat, mask, _ = _adjoint_lattice(b, adims)
+    an = int(np.prod(adims))
+    adj_ms, traj_ms, _ = _adjoint_step_and_recompute(b, lat, 20, 4)
+    fl = float((mask == 0).mean())
+    r = {"adjoint": b.record(an, adj_ms, ADJ_BYTES, frac_fluid=round(fl * ADJ_BYTES * an / (adj_ms * 1e-3) / 1e9
+                                                                       / HBM_PEAK_GBS, 4)),
+         "recompute": b.record(an, traj_ms, bytes_per_node("f32", True, True), launch="clbm_trajectory, 4 states"),
+         "adjoint_with_recompute_mlups": round(an / ((adj_ms + traj_ms) * 1e-3) / 1e6, 1),
+         "solid_fraction": round(float(mask.mean()), 4)}
+    b.done(lat)
+    return r
+
+
+VARIANTS = {
+    "kolmogorov_512_f32_single": v_kolmogorov_single,
+    "kolmogorov_512_f32_dense": v_kolmogorov_dense,
+    "kolmogorov_512_f64": v_kolmogorov_storage("f64"),
+    "kolmogorov_512_f16": v_kolmogorov_storage("f16"),
+    "kolmogorov_512_bf16": v_kolmogorov_storage("bf16"),
+    "kolmogorov_512_general_f32": v_kolmogorov_general,
+    "kolmogorov_512_mrt_f32": v_kolmogorov_mrt,
+    "kolmogorov_512_d3q19_f32": v_kolmogorov_d3q19("f32"),
+    "kolmogorov_512_d3q19_f64": v_kolmogorov_d3q19("f64"),
+    "kolmogorov_512_d3q19_f16": v_kolmogorov_d3q19("f16"),
+    "cavity_256_cascaded_f32": v_cavity("cascaded"),
+    "cavity_256_mrt_f32": v_cavity("mrt"),
+    "table_I_latency": v_table_I_latency,
+    "table_I_bandwidth": v_table_I_bandwidth,
+    "taylor_green_128_f64": v_taylor_green("f64"),
+    "taylor_green_128_f32": v_taylor_green("f32"),
+    "porous_640x320x320_f32": v_porous(False),
+    "porous_640x320x320_general_f32": v_porous(True),
+    "adjoint_channel_64_f32": v_adjoint_channel,
+    "adjoint_porous_256x128x128_f32": v_adjoint_porous_crop,
+    "adjoint_porous_640x320x320_f32": v_adjoint_porous_full,
+}
+
+
+# ------------------------------------------------------------------------------------------------ headline
+def headline(b: Bench, args):
+    torch = b.torch
+    lat = b.kolmogorov_lattice()
     lat.step(args.warmup)
     torch.cuda.synchronize()
     fused = lat.uses_fused_pairs
@@ -175,34 +572,26 @@ def main():
     event_ms = ev0.elapsed_time(ev1)
     kernel_ms = event_ms / launches
     ms_per_step = wall * 1e3 / args.steps
+    nodes = b.nodes
     mlups = nodes * args.steps / wall / 1e6
     bpn = bytes_per_node("f32", True, False)
     # algorithmic bytes of the node updates done in the timed region, per unit of kernel time
     achieved = bpn * nodes * args.steps / (event_ms * 1e-3) / 1e9
     log(f"[bench] f32 ({'two fused steps per launch' if fused else 'one step per launch'}): {ms_per_step:.3f} "
         f"ms/step wall, {kernel_ms:.3f} ms/launch, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic")
-    _, _, tot, nbad = lat.moments(fields=False)
+    _, _, _, nbad = lat.moments(fields=False)
     if nbad:
         log(f"[bench] WARNING: {nbad} non-finite nodes")
-
     if args.copy_calibration:
         tmp = torch.empty_like(lat.state)
         for _ in range(5):
             lat.ctx.copy(lat.state, tmp)
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record()
-        for _ in range(5):
-            lat.ctx.copy(lat.state, tmp)
-        c1.record()
-        torch.cuda.synchronize()
-        cms = c0.elapsed_time(c1) / 5
+        cms = b.ms(lambda: [lat.ctx.copy(lat.state, tmp) for _ in range(5)], 5, reps=3)
         log(f"[bench] copy {lat.state.numel() * 4 / 1e9:.2f} GB: {cms:.3f} ms = "
             f"{2 * lat.state.numel() * 4 / (cms * 1e-3) / 1e9:.0f} GB/s read+write")
         del tmp
-
-    traffic = pmc_traffic(PMC_FUSED if fused else PMC_SINGLE, L, fused)
+    traffic = pmc_traffic(PMC_FUSED if fused else PMC_SINGLE, b.L, fused)
     kname = "k_step2<float, force field> (two fused steps)" if fused else "k_step<float, periodic, force field>"
-
     result = {
         # the headline metric; value = FP32-storage MLUPS of the fused D3Q27 cascaded step, roofline.frac its
         # HBM fraction; FP64/FP16/BF16 storage, the adjoint and the errors against FP64 are under variants
@@ -220,11 +609,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"kolmogorov_{L}^3",
+            "workload": f"kolmogorov_{b.L}^3",
             "nodes": nodes,
             "storage": "f32 deviations f - w",
             "force": "per-node FP32 field, F0 = 1e-5, k = 4",
-            "nu": nu,
+            "nu": 0.005,
             "boundaries": "periodic",
             "bytes_per_node": bpn,
             "plane_stride": lat.P,
@@ -246,379 +635,161 @@ def main():
             "traffic_frac": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
     }
-    if fused:
-        # the same lattice with one step per launch, for comparison
-        lat.set_fused_steps(False)
-        ms1 = time_steps(torch, lat, 10)
-        lat.set_fused_steps(None)
-        result["single_step_kernel"] = {
-            "mlups": round(nodes / (ms1 * 1e-3) / 1e6, 1), "kernel_ms": round(ms1, 4),
-            "frac": round(bpn * nodes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": pmc_traffic(PMC_SINGLE, L, False)}
-        log(f"[bench] f32 single steps: {result['single_step_kernel']}")
-    if args.primary_only:
-        print(json.dumps(result), flush=True)
+    step_ms = event_ms / args.steps
+    b.done(lat)
+    return result, b.record(nodes, step_ms, bpn, launch="two fused steps" if fused else "one step")
+
+
+def accuracy(b: Bench):
+    torch = b.torch
+    steps = 500
+    acc = {}
+    l64 = b.kolmogorov_lattice("f64")
+    l64.step(steps)
+    _, u64, _, _ = l64.moments()
+    b.done(l64)
+    nrm = torch.linalg.vector_norm(u64).item()
+    umax = u64.abs().max().item()
+    for storage in ("f32", "f16", "bf16"):
+        ls = b.kolmogorov_lattice(storage)
+        ls.step(steps)
+        _, us, _, nb = ls.moments()
+        d = us - u64
+        acc[storage] = {"l2_rel": float(torch.linalg.vector_norm(d).item() / nrm),
+                        "max_rel": float(d.abs().max().item() / umax), "nonfinite": int(nb)}
+        log(f"[bench] accuracy {storage} after {steps} steps: {acc[storage]}")
+        b.done(ls)
+        del us, d
+    acc["reference"] = f"FP64 storage, same inputs, {steps} steps; u_max = {umax:.4e}"
+    acc["targets"] = "FP32: L2-relative below 1e-5 (its max-relative error is stated beside it)"
+    del u64
+    return acc
+
+
+def cpu_baseline(b: Bench, args):
+    import oracle
+
+    np, wl = b.np, b.workloads
+    _, _, F, u0 = b.kolmogorov()
+    dims, L = b.dims, b.L
+    wd = (128, 128, 32)
+    g = oracle.Geometry(dims, (0, 0, 0), (0, 0, 0), wd)
+    sl = (slice(0, wd[2]), slice(0, wd[1]), slice(0, wd[0]))
+    rates = wl.rates(0.005)
+    f0 = oracle.init(g, None, np.ascontiguousarray(u0[(slice(None),) + sl]))
+    Fw = np.ascontiguousarray(F[(slice(None),) + sl])
+    t0 = time.perf_counter()
+    f = oracle.step(g, f0, rates, force_field=Fw)
+    t1 = time.perf_counter() - t0
+    nsteps = max(1, min(50, int(args.cpu_seconds / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        f = oracle.step(g, f, rates, force_field=Fw)
+    tc = time.perf_counter() - t0
+    wn = int(np.prod(wd))
+    res = {"value": round(wn * nsteps / tc / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
+           "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"{wd[0]}x{wd[1]}x{wd[2]} window of the {L}^3 Kolmogorov lattice, {nsteps} steps, FP64 dense "
+                     f"27x27 oracle, {tc:.1f} s"}
+    budget = args.cpu_seconds / 2
+
+    def timed_run(geom, f, rates_, max_steps, **kw):
+        # one step to size the run, then as many as fit the budget (at most max_steps)
+        t0 = time.perf_counter()
+        f = oracle.step(geom, f, rates_, **kw)
+        t1 = time.perf_counter() - t0
+        n = max(1, min(max_steps, int(budget / max(t1, 1e-4))))
+        t0 = time.perf_counter()
+        for _ in range(n):
+            f = oracle.step(geom, f, rates_, **kw)
+        dt = time.perf_counter() - t0
+        return geom.n * n / dt / 1e6, n, dt
+
+    nthreads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    w1 = (64, 64, 16)
+    g1 = oracle.Geometry(dims, (0, 0, 0), (0, 0, 0), w1)
+    s1 = (slice(0, w1[2]), slice(0, w1[1]), slice(0, w1[0]))
+    f1 = oracle.init(g1, None, np.ascontiguousarray(u0[(slice(None),) + s1]))
+    m1, n1, d1 = timed_run(g1, f1, rates, 50, force_field=np.ascontiguousarray(F[(slice(None),) + s1]))
+    oracle.set_num_threads(nthreads)
+    res["single_core"] = {"value": round(m1, 4), "cores": 1,
+                          "sample": f"{w1[0]}x{w1[1]}x{w1[2]} window of the same lattice, {n1} steps, {d1:.1f} s"}
+    pc = wl.POISEUILLE
+    gp = oracle.Geometry(pc.dims, pc.walls)
+    mp, npo, dp_ = timed_run(gp, oracle.init(gp), pc.rates(), pc.steps, force=pc.force_uniform)
+    tc2 = wl.TGV128
+    gt = oracle.Geometry(tc2.dims, tc2.walls)
+    rt0, ut0 = wl.taylor_green_3d(tc2.dims, 0.04)
+    mt, ntg, dtg = timed_run(gt, oracle.init(gt, rt0, ut0), tc2.rates(), tc2.steps)
+    res["other_workloads"] = {
+        pc.name: {"value": round(mp, 4), "steps": npo, "of_steps": pc.steps, "seconds": round(dp_, 2)},
+        tc2.name: {"value": round(mt, 4), "steps": ntg, "of_steps": tc2.steps, "seconds": round(dtg, 2)},
+        "note": "bounded samples: as many steps of each workload as fit the time budget"}
+    log(f"[bench] cpu baseline: {res}")
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--size", type=int, default=512, help="edge of the cubic Kolmogorov lattice")
+    ap.add_argument("--only", default="", help="comma-separated variant names (or 'headline'); no headline line")
+    ap.add_argument("--primary-only", action="store_true", help="time only the FP32 step (for profilers)")
+    ap.add_argument("--copy-calibration", action="store_true", help="also run the plain copy kernel (PMC scale)")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    only = [s for s in args.only.split(",") if s]
+    unknown = [s for s in only if s not in VARIANTS and s != "headline"]
+    if unknown:
+        print(f"unknown variants {unknown}; known: headline, {', '.join(VARIANTS)}", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    b = Bench(args)
+    log(f"[bench] Kolmogorov {b.dims}, nu=0.005; kernel source {kernel_sha()}")
+
+    if only:
+        out = {"only": only, "variants": {}}
+        for name in only:
+            if name == "headline":
+                out["headline"], _ = headline(b, args)
+                continue
+            log(f"[bench] {name}")
+            out["variants"][name] = VARIANTS[name](b)
+            log(f"[bench] {name}: {out['variants'][name]}")
+        print(json.dumps(out), flush=True)
         return
 
-    # the same workload with dense planes (plane stride = N, a power of two here)
-    ld = Lattice(dims, (0, 0, 0), "f32", rates, force_field=F32_dev, device=dev, plane_stride=0)
-    ld.init(None, u0_dev)
-    ld.step(4)
-    msd = time_steps(torch, ld, 10)
-    ld.set_fused_steps(False)
-    msd1 = time_steps(torch, ld, 10)
-    result["dense_planes"] = {"plane_stride": ld.P, "fused_mlups": round(nodes / (msd * 1e-3) / 1e6, 1),
-                              "single_step_mlups": round(nodes / (msd1 * 1e-3) / 1e6, 1)}
-    log(f"[bench] dense planes: {result['dense_planes']}")
-    ld.close()
-    del ld
-
-    lat.close()
-    del lat
-    torch.cuda.empty_cache()
-
-    # ------------------------------------------------------------------ other storage types, same lattice
-    variants = {}
-    if not args.no_variants:
-        for storage in ("f64", "f16", "bf16"):
-            field = F32_dev
-            if storage == "f64":
-                F64_dev = torch.from_numpy(F).to(dev)
-                field = F64_dev
-            lv = Lattice(dims, (0, 0, 0), storage, rates, force_field=field, device=dev)
-            lv.init(None, u0_dev)
-            lv.step(3)
-            ms = time_steps(torch, lv, 10)
-            b = bytes_per_node(storage, True, False)
-            variants[f"kolmogorov_{L}_{storage}"] = {
-                "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4),
-                "launch": "two fused steps" if lv.uses_fused_pairs else "one step",
-                "bytes_per_node": b, "frac": round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-            if lv.uses_fused_pairs:
-                lv.set_fused_steps(False)
-                ms1 = time_steps(torch, lv, 10)
-                lv.set_fused_steps(None)
-                variants[f"kolmogorov_{L}_{storage}"]["single_step_mlups"] = round(nodes / (ms1 * 1e-3) / 1e6, 1)
-            log(f"[bench] {storage}: {ms:.3f} ms/step, {variants[f'kolmogorov_{L}_{storage}']}")
-            lv.close()
-            del lv
-            torch.cuda.empty_cache()
-        # the raw-moment MRT of Appendix B (Guo forcing) on the same lattice and force field, FP32
-        lv = Lattice(dims, (0, 0, 0), "f32", rates, force_field=F32_dev, device=dev, collision="mrt")
-        lv.init(None, u0_dev)
-        lv.step(4)
-        ms = time_steps(torch, lv, 10)
-        b = bytes_per_node("f32", True, False)
-        variants[f"kolmogorov_{L}_mrt_f32"] = {
-            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
-            "launch": "two fused steps" if lv.uses_fused_pairs else "one step", "bytes_per_node": b,
-            "frac": round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        log(f"[bench] MRT f32: {variants[f'kolmogorov_{L}_mrt_f32']}")
-        lv.close()
-        del lv
-        torch.cuda.empty_cache()
-
-        # the D3Q19 scheme of Appendix A on the same lattice and force field
-        for storage in ("f32", "f64", "f16"):
-            field = F32_dev if storage != "f64" else F64_dev
-            lv = Lattice(dims, (0, 0, 0), storage, rates, force_field=field, device=dev, lattice="d3q19")
-            lv.init(None, u0_dev)
-            lv.step(3)
-            ms = time_steps(torch, lv, 10)
-            b = bytes_per_node(storage, True, False, q=19)
-            key = f"kolmogorov_{L}_d3q19_{storage}"
-            variants[key] = {"mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4),
-                             "bytes_per_node": b, "frac": round(b * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-            log(f"[bench] D3Q19 {storage}: {variants[key]}")
-            lv.close()
-            del lv
-            torch.cuda.empty_cache()
-        step_ms = event_ms / args.steps
-        variants[f"kolmogorov_{L}_f32"] = {"mlups": round(nodes / (step_ms * 1e-3) / 1e6, 1),
-                                           "ms_per_step": round(step_ms, 4), "bytes_per_node": bpn,
-                                           "frac": round(achieved / HBM_PEAK_GBS, 4)}
-        f64k = variants[f"kolmogorov_{L}_f64"]["kernel_ms"]
-        result["speedup_f32_over_f64"] = round(f64k / step_ms, 3)
-
-        # lid-driven cavity 256^3 (all walls, lid moving with U = 0.1), cascaded and MRT, FP32: the walled path
-        cdims = (256, 256, 256)
-        for coll in ("cascaded", "mrt"):
-            lv = Lattice(cdims, (1, 1, 1), "f32", workloads.rates(0.1 * 256 / 400.0), device=dev, collision=coll,
-                         wall_velocity={(1, 1): (0.1, 0.0, 0.0)})
-            lv.init()
-            lv.step(3)
-            ms = time_steps(torch, lv, 10)
-            b = bytes_per_node("f32", False, False)
-            variants[f"cavity_256_{coll}_f32"] = {
-                "mlups": round(256 ** 3 / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
-                "launch": "two fused steps" if lv.uses_fused_pairs else "one step", "bytes_per_node": b,
-                "frac": round(b * 256 ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-            if lv.uses_fused_pairs:
-                lv.set_fused_steps(False)
-                ms1 = time_steps(torch, lv, 10)
-                variants[f"cavity_256_{coll}_f32"]["single_step_mlups"] = round(256 ** 3 / (ms1 * 1e-3) / 1e6, 1)
-            log(f"[bench] cavity {coll}: {variants[f'cavity_256_{coll}_f32']}")
-            lv.close()
-            del lv
-        torch.cuda.empty_cache()
-
-        # Table I's workload: 10 000 steps of the shear wave on 5 x ny x 5, the cascaded scheme against
-        # the SRT (BGK) LBM with the discrete equilibrium -- the MRT with every rate equal -- in FP64
-        table1 = {}
-        for ny in (101, 201, 401):
-            sdims = (5, ny, 5)
-            phi = 2 * np.pi / ny
-            us = np.zeros((3, 5, ny, 5))
-            us[0] = (1e-3 * np.sin(phi * np.arange(ny)))[None, :, None]
-            us[1] = 0.3 / np.sqrt(3.0)
-            row = {}
-            for name, coll, r in (("t_C", "cascaded", workloads.rates(0.05)),
-                                  ("t_S", "mrt", np.full(10, workloads.s2_from_nu(0.05)))):
-                lv = Lattice(sdims, (0, 0, 0), "f64", r, device=dev, collision=coll)
-                lv.init(None, us)
-                lv.step(100)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                lv.step(10000)
-                torch.cuda.synchronize()
-                row[name] = round(time.perf_counter() - t0, 5)
-                # the same 10 000 steps as 100 replays of a HIP graph of 100 launches (launch-bound lattices)
-                graph = graph_of_steps(torch, lv, 100)
-                graph.replay()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(100):
-                    graph.replay()
-                torch.cuda.synchronize()
-                row[name + "_graph"] = round(time.perf_counter() - t0, 5)
-                del graph
-                lv.close()
-            row["t_C/t_S"] = round(row["t_C"] / row["t_S"], 3)
-            row["t_C/t_S_graph"] = round(row["t_C_graph"] / row["t_S_graph"], 3)
-            table1[f"5x{ny}x5"] = row
-        variants["table_I_shear_wave_10000_steps_f64"] = table1
-        log(f"[bench] Table I workload: {table1}")
-
-        # plain kernel on the 128^3 Taylor-Green case
-        tdims = (128, 128, 128)
-        rho_t, u_t = workloads.taylor_green_3d(tdims, 0.04)
-        for storage in ("f64", "f32"):
-            lt = Lattice(tdims, (0, 0, 0), storage, workloads.rates(0.01), device=dev)
-            lt.init(rho_t, u_t)
-            lt.step(3)
-            ms = time_steps(torch, lt, 50)
-            b = bytes_per_node(storage, False, False)
-            variants[f"taylor_green_128_{storage}"] = {
-                "mlups": round(128 ** 3 / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 4), "bytes_per_node": b,
-                "frac": round(b * 128 ** 3 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "note": "2 x 226-453 MB working set: partly served by the 256 MB last-level cache"}
-            lt.close()
-
-        # porous duct 640x320x320, FP32, walls in y and z, spheres (solid fraction 0.2)
-        pdims = (640, 320, 320)
-        pmask, _, _ = workloads.porous_spheres(pdims, (0, 1, 1), 6.0, 12.0, 0.2, workloads.SEED)
-        lp = Lattice(pdims, (0, 1, 1), "f32", workloads.rates(0.02), force=(2e-6, 0, 0), solid=pmask, device=dev)
-        lp.init()
-        lp.step(3)
-        ms = time_steps(torch, lp, 10)
-        pn = int(np.prod(pdims))
-        fluid = int((pmask == 0).sum())
-        pb = 2 * 27 * 4 * fluid + pn  # populations of fluid nodes + the solid mask
-        variants["porous_640x320x320_f32"] = {
-            "mlups": round(pn / (ms * 1e-3) / 1e6, 1), "mflups_fluid": round(fluid / (ms * 1e-3) / 1e6, 1),
-            "ms_per_step": round(ms, 4), "launch": "two fused steps" if lp.uses_fused_pairs else "one step",
-            "bytes_per_node": round(pb / pn, 2),
-            "frac": round(pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "solid_fraction": round(1 - fluid / pn, 4)}
-        if lp.uses_fused_pairs:
-            lp.set_fused_steps(False)
-            ms1 = time_steps(torch, lp, 10)
-            variants["porous_640x320x320_f32"]["single_step_mlups"] = round(pn / (ms1 * 1e-3) / 1e6, 1)
-        log(f"[bench] porous: {variants['porous_640x320x320_f32']}")
-        lp.close()
-        del lp
-        torch.cuda.empty_cache()
-
-        # end-to-end gradient on the adjoint channel case: 64^3, T = 200, checkpoint every 20, FP32
-        from paper_1801_04586_amd.adjoint import flow_loss
-
-        cdims, T, K = (64, 64, 64), 200, 20
-        Fc = workloads.gaussian_force(cdims, 1e-6, workloads.SEED)
-        lc = Lattice(cdims, (0, 1, 0), "f32", workloads.rates(0.05), force_field=Fc, device=dev)
-        lc.init()
-        s0 = lc.state.clone()
-        utc = torch.from_numpy(workloads.channel_target(cdims, (0, 1, 0), 1e-4)).to(dev, torch.float32)
-        Ft = torch.from_numpy(Fc).to(dev, torch.float32)
-        st = torch.from_numpy(workloads.rates(0.05))
-        times = []
-        for _ in range(3):
-            Fr, sr = Ft.clone().requires_grad_(True), st.clone().requires_grad_(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            flow_loss(Fr, sr, lc, s0, utc, T, K).backward()
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        cn = int(np.prod(cdims))
-        tbest = min(times)
-        variants["adjoint_channel_64_f32_T200_K20"] = {
-            "gradient_seconds": round(tbest, 4),
-            "node_updates_per_s_M": round(cn * T * 3 / tbest / 1e6, 1),
-            "note": "forward T steps + recompute T steps + T adjoint steps, 64^3 (cache-resident, launch-bound)"}
-        log(f"[bench] adjoint channel: {variants['adjoint_channel_64_f32_T200_K20']}")
-        lc.close()
-
-        # adjoint step on a porous crop (FP32, walls y/z, spheres, per-node force field)
-        adims = (256, 128, 128)
-        mask, _, _ = workloads.porous_spheres(adims, (0, 1, 1), 6.0, 12.0, 0.2, workloads.SEED)
-        Fa = workloads.gaussian_force(adims, 1e-6, workloads.SEED)
-        la = Lattice(adims, (0, 1, 1), "f32", workloads.rates(0.02), force=(2e-6, 0, 0), force_field=Fa, solid=mask,
-                     device=dev)
-        la.init()
-        la.step(5)
-        ut = torch.zeros((3,) + la.shape, dtype=torch.float32, device=dev)
-        lam = torch.empty((27,) + la.shape, dtype=torch.float32, device=dev)
-        lam2 = torch.empty_like(lam)
-        gF = torch.zeros((3,) + la.shape, dtype=torch.float32, device=dev)
-        gs = torch.zeros(10, dtype=torch.float64, device=dev)
-        la.ctx.loss_seed(la.state, ut, lam, gF, None)
-        an = int(np.prod(adims))
-        reps = []
-        for _ in range(9):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(10):
-                la.ctx.adjoint_step(la.state, lam, lam2, gF, gs)
-                lam, lam2 = lam2, lam
-            b.record()
-            b.synchronize()
-            reps.append(a.elapsed_time(b) / 10)
-        ams = trimmed_mean(reps)
-        fwd = time_steps(torch, la, 10)
-        # adjoint bytes per fluid node: state 27x4 + lambda in/out 2x27x4 + dJ/dF rmw 2x3x4 + force 3x4 + mask
-        ab = 27 * 4 * 3 + 24 + 12 + 1
-        variants["adjoint_porous_256x128x128_f32"] = {
-            "adjoint_mlups": round(an / (ams * 1e-3) / 1e6, 1), "adjoint_kernel_ms": round(ams, 4),
-            "with_recompute_mlups": round(an / ((ams + fwd) * 1e-3) / 1e6, 1),
-            "bytes_per_node": ab, "frac": round(ab * an / (ams * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "solid_fraction": round(float(mask.mean()), 4)}
-        log(f"[bench] adjoint: {variants['adjoint_porous_256x128x128_f32']}")
-        # end to end: gradient of the flow loss on the crop, T = 40 steps, checkpoint every K = 20
-        from paper_1801_04586_amd.adjoint import flow_loss
-
-        Ta, Ka = 40, 20
-        s0a = la.state.clone()
-        Fta = torch.from_numpy(Fa).to(dev, torch.float32)
-        sta = torch.from_numpy(workloads.rates(0.02))
-        times = []
-        for _ in range(3):
-            Fr, sr = Fta.clone().requires_grad_(True), sta.clone().requires_grad_(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            flow_loss(Fr, sr, la, s0a, ut, Ta, Ka).backward()
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        tg = min(times)
-        variants["adjoint_porous_256x128x128_f32"].update({
-            "gradient_T40_K20_seconds": round(tg, 4),
-            "gradient_node_updates_per_s_M": round(an * Ta * 3 / tg / 1e6, 1)})
-        log(f"[bench] adjoint gradient: {variants['adjoint_porous_256x128x128_f32']}")
-        la.close()
-        del la, lam, lam2, gF
-        torch.cuda.empty_cache()
-    result["variants"] = variants
-
-    # ------------------------------------------------------------------ accuracy of storage types vs FP64
-    if not args.no_accuracy:
-        steps = 500
-        acc = {}
-        if F64_dev is None:
-            F64_dev = torch.from_numpy(F).to(dev)
-        l64 = Lattice(dims, (0, 0, 0), "f64", rates, force_field=F64_dev, device=dev)
-        l64.init(None, u0_dev)
-        l64.step(steps)
-        _, u64, _, _ = l64.moments()
-        l64.close()
-        del l64
-        torch.cuda.empty_cache()
-        nrm = torch.linalg.vector_norm(u64).item()
-        umax = u64.abs().max().item()
-        for storage in ("f32", "f16", "bf16"):
-            ls = Lattice(dims, (0, 0, 0), storage, rates, force_field=F32_dev, device=dev)
-            ls.init(None, u0_dev)
-            ls.step(steps)
-            _, us, _, nb = ls.moments()
-            d = us - u64
-            acc[storage] = {"l2_rel": float(torch.linalg.vector_norm(d).item() / nrm),
-                            "max_rel": float(d.abs().max().item() / umax), "nonfinite": int(nb)}
-            log(f"[bench] accuracy {storage} after {steps} steps: {acc[storage]}")
-            ls.close()
-            del ls, us, d
-            torch.cuda.empty_cache()
-        acc["reference"] = f"FP64 storage, same inputs, {steps} steps; u_max = {umax:.4e}"
-        result["accuracy_vs_f64"] = acc
-        del u64
-
-    # ------------------------------------------------------------------ CPU oracle on a bounded sample
-    if not args.no_cpu:
-        import oracle
-
-        wd = (128, 128, 32)
-        g = oracle.Geometry(dims, (0, 0, 0), (0, 0, 0), wd)
-        sl = (slice(0, wd[2]), slice(0, wd[1]), slice(0, wd[0]))
-        f0 = oracle.init(g, None, np.ascontiguousarray(u0[(slice(None),) + sl]))
-        Fw = np.ascontiguousarray(F[(slice(None),) + sl])
-        t0 = time.perf_counter()
-        f = oracle.step(g, f0, rates, force_field=Fw)
-        t1 = time.perf_counter() - t0
-        nsteps = max(1, min(50, int(args.cpu_seconds / max(t1, 1e-3))))
-        t0 = time.perf_counter()
-        for _ in range(nsteps):
-            f = oracle.step(g, f, rates, force_field=Fw)
-        tc = time.perf_counter() - t0
-        wn = int(np.prod(wd))
-        result["cpu_baseline"] = {
-            "value": round(wn * nsteps / tc / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{wd[0]}x{wd[1]}x{wd[2]} window of the {L}^3 Kolmogorov lattice, {nsteps} steps, FP64 dense "
-                      f"27x27 oracle, {tc:.1f} s"}
-        budget = args.cpu_seconds / 2
-
-        def timed_run(geom, f, rates_, max_steps, **kw):
-            # one step to size the run, then as many as fit the budget (at most max_steps)
-            t0 = time.perf_counter()
-            f = oracle.step(geom, f, rates_, **kw)
-            t1 = time.perf_counter() - t0
-            n = max(1, min(max_steps, int(budget / max(t1, 1e-4))))
-            t0 = time.perf_counter()
-            for _ in range(n):
-                f = oracle.step(geom, f, rates_, **kw)
-            dt = time.perf_counter() - t0
-            return geom.n * n / dt / 1e6, n, dt
-
-        # one core, a smaller window of the same workload
-        nthreads = oracle.num_threads()
-        oracle.set_num_threads(1)
-        w1 = (64, 64, 16)
-        g1 = oracle.Geometry(dims, (0, 0, 0), (0, 0, 0), w1)
-        s1 = (slice(0, w1[2]), slice(0, w1[1]), slice(0, w1[0]))
-        f1 = oracle.init(g1, None, np.ascontiguousarray(u0[(slice(None),) + s1]))
-        m1, n1, d1 = timed_run(g1, f1, rates, 50, force_field=np.ascontiguousarray(F[(slice(None),) + s1]))
-        oracle.set_num_threads(nthreads)
-        result["cpu_baseline"]["single_core"] = {
-            "value": round(m1, 4), "cores": 1,
-            "sample": f"{w1[0]}x{w1[1]}x{w1[2]} window of the same lattice, {n1} steps, {d1:.1f} s"}
-        # the force-driven channel (16x32x16, FP64, 3000 steps) and the 128^3 Taylor-Green vortex, all cores
-        pc = workloads.POISEUILLE
-        gp = oracle.Geometry(pc.dims, pc.walls)
-        mp, npo, dp_ = timed_run(gp, oracle.init(gp), pc.rates(), pc.steps, force=pc.force_uniform)
-        tc2 = workloads.TGV128
-        gt = oracle.Geometry(tc2.dims, tc2.walls)
-        rt0, ut0 = workloads.taylor_green_3d(tc2.dims, 0.04)
-        mt, ntg, dtg = timed_run(gt, oracle.init(gt, rt0, ut0), tc2.rates(), tc2.steps)
-        result["cpu_baseline"]["other_workloads"] = {
-            pc.name: {"value": round(mp, 4), "steps": npo, "seconds": round(dp_, 2)},
-            tc2.name: {"value": round(mt, 4), "steps": ntg, "seconds": round(dtg, 2)}}
-        log(f"[bench] cpu baseline: {result['cpu_baseline']}")
-
+    result, head_rec = headline(b, args)
+    if not args.primary_only:
+        variants = {HEADLINE: head_rec}
+        if not args.no_variants:
+            for name, fn in VARIANTS.items():
+                log(f"[bench] {name}")
+                variants[name] = fn(b)
+                log(f"[bench] {name}: {variants[name]}")
+            result["speedup_f32_over_f64"] = round(variants["kolmogorov_512_f64"]["ms_per_step"] /
+                                                   head_rec["ms_per_step"], 3)
+        result["variants"] = variants
+        if not args.no_accuracy:
+            result["accuracy_vs_f64"] = accuracy(b)
+    if not args.no_cpu and not args.primary_only:
+        result["cpu_baseline"] = cpu_baseline(b, args)
     result["context"] = {
         "paper_cpu": "0.45 MLUPS: C++ CLBM, i7-6500U laptop, 5x101x5 shear wave (Table I), context only",
         "paper_table_I_seconds": {"5x101x5": [56.028, 26.042, 2.151], "5x201x5": [111.838, 51.728, 2.162],

@@ -210,10 +210,9 @@ int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result);
 /* nsteps steps from the state in src, keeping every state (not in the paper; for the adjoint's
  * recomputation): states (host array of nsteps device state
  * buffers, distinct from src and from one another) gets the state after k + 1 steps in states[k]; src
- * is not modified.  Where
- * clbm_run fuses pairs of steps, one launch runs two steps and also stores the state between them
- * (read once, written twice per two steps instead of two reads and two writes); the results are
- * bitwise those of clbm_step calls.  nsteps >= 0 (0: nothing happens). */
+ * is not modified.  Every step is one clbm_step launch (bitwise the same results), without
+ * clbm_run's fused pairs, since every state has to be written anyway.  nsteps >= 0 (0: nothing
+ * happens). */
 int clbm_trajectory(clbm_ctx *ctx, const void *src, void *const *states, int32_t nsteps);
 
 /* Option flags (clbm_set_options). */

@@ -9,10 +9,10 @@ the hand-written adjoint kernels (``clbm_loss_seed``, ``clbm_adjoint_step``):
   * forward: T steps through clbm_run (fused step pairs where it uses them),
     a copy of the state kept every K steps (checkpoints);
   * backward: segments from last to first; the K - 1 states after a
-    segment's checkpoint are recomputed from it by clbm_trajectory (fused
-    step pairs that also store the state between them, where clbm_run fuses;
-    bitwise identical to the original run either way), then the adjoint
-    steps walk back through the checkpoint and those states.
+    segment's checkpoint are recomputed from it by clbm_trajectory (single
+    steps, bitwise identical to the original run, whose fused pairs are
+    bitwise two single steps), then the adjoint steps walk back through the
+    checkpoint and those states.
 
 Memory: ceil(T/K) checkpoints + K - 1 segment states + two adjoint buffers.
 """

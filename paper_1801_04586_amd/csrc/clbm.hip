@@ -24,6 +24,7 @@ thread_local char g_err[512] = "no error";
 
 }  // namespace
 
+
 struct clbm_ctx {
     clbm_desc d;
     hipStream_t stream;
@@ -34,7 +35,7 @@ struct clbm_ctx {
     uint32_t *links;   // [N] link table (k_links) when the lattice has solid nodes, else NULL
     uint32_t options;  // CLBM_OPT_* flags
     int num_cu;        // compute units of the device
-    int t2_slots[2][2][2][2];  // resident blocks of the fused kernel, by (links, force field, collision, keep); 0 = unknown
+    int t2_slots[2][2][2];  // resident blocks of the fused kernel, by (links, force field, collision); 0 = unknown
     char err[512];
 };
 
@@ -290,9 +291,7 @@ uint32_t fused_chunks(uint32_t tiles, uint32_t nz, uint32_t slots)
     return best;
 }
 
-// Two steps src -> dst in one launch; with mid != NULL the state after the first step is also
-// stored there.
-int launch_step2(clbm_ctx *c, const void *src, void *dst, void *mid = nullptr)
+int launch_step2(clbm_ctx *c, const void *src, void *dst)
 {
     T2Geom tg;
     tg.tiles_x = (c->geom.nx + kT2X - 1) / kT2X;
@@ -304,14 +303,13 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst, void *mid = nullptr)
         using R = typename Traits<S>::R;
         constexpr bool FIELD = decltype(field_tag)::value;
         constexpr bool SOLID = decltype(solid_tag)::value;
-        auto launch = [&](auto cc, auto keep_tag) {
+        auto launch = [&](auto cc) {
             constexpr int C = decltype(cc)::value;
-            constexpr bool KEEP = decltype(keep_tag)::value;
-            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0][KEEP ? 1 : 0];
+            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0];
             if (slots == 0) {
                 int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID, KEEP>,
-                                                                 kT2Block, 0) != hipSuccess ||
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID>, kT2Block,
+                                                                 0) != hipSuccess ||
                     per_cu < 1)
                     per_cu = 1;
                 slots = per_cu * c->num_cu;
@@ -320,17 +318,13 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst, void *mid = nullptr)
             tg.zchunk = (c->geom.nz + nchunks_req - 1) / nchunks_req;
             const uint32_t nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
             const unsigned blocks = tiles * nchunks;
-            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID, KEEP>), dim3(blocks), dim3(kT2Block), 0, c->stream,
-                               static_cast<const S *>(src), static_cast<S *>(dst), static_cast<S *>(mid), c->geom,
-                               tg, c->links, static_cast<const R *>(c->d.force), make_forcing<R>(c->d),
-                               make_rates<R>(c->d.s));
+            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID>), dim3(blocks), dim3(kT2Block), 0, c->stream,
+                               static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg, c->links,
+                               static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
             return check_launch(c, "fused two-step kernel launch");
         };
-        auto keep = [&](auto cc) {
-            return mid ? launch(cc, std::true_type{}) : launch(cc, std::false_type{});
-        };
-        if (coll == kCascadedHigh1) return keep(std::integral_constant<int, kCascadedHigh1>{});
-        return keep(std::integral_constant<int, kCascaded>{});
+        if (coll == kCascadedHigh1) return launch(std::integral_constant<int, kCascadedHigh1>{});
+        return launch(std::integral_constant<int, kCascaded>{});
     };
     if (c->links)
         return c->d.force != nullptr ? go(float{}, std::true_type{}, std::true_type{})
@@ -568,15 +562,11 @@ int clbm_trajectory(clbm_ctx *ctx, const void *src, void *const *states, int32_t
     std::sort(seen.begin(), seen.end());
     if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
         return fail(ctx, CLBM_EINVAL, "src and the state buffers must be distinct");
+    // single steps: each state has to be written anyway, and a fused pair that also stores the state
+    // between its steps moved its 1.5x bytes at the fused kernel's lower bandwidth, slower than two
+    // single steps
     const void *cur = src;
-    int32_t k = 0;
-    if (fused_pairs(ctx))
-        for (; k + 2 <= nsteps; k += 2) {
-            const int rc = launch_step2(ctx, cur, states[k + 1], states[k]);
-            if (rc) return rc;
-            cur = states[k + 1];
-        }
-    for (; k < nsteps; ++k) {
+    for (int32_t k = 0; k < nsteps; ++k) {
         const int rc = launch_step(ctx, cur, states[k]);
         if (rc) return rc;
         cur = states[k];
@@ -703,14 +693,25 @@ int clbm_set_populations(clbm_ctx *ctx, const double *f, void *state)
     });
 }
 
-int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, void *dJdF,
-                      double *dJds)
+}  // extern "C"
+
+namespace {
+
+int check_adjoint_args(clbm_ctx *ctx, const void *state_t, const void *lam_next, const void *lam_out,
+                       const void *dJdF, const double *dJds)
 {
-    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
     if (!state_t || !lam_next || !lam_out || !aligned(state_t) || !aligned(lam_next) || !aligned(lam_out))
         return fail(ctx, CLBM_EINVAL, "bad adjoint buffers");
     if (lam_next == lam_out) return fail(ctx, CLBM_EINVAL, "lam_next and lam_out must be distinct");
     if ((dJdF && !aligned(dJdF)) || (dJds && !aligned(dJds))) return fail(ctx, CLBM_EINVAL, "dJdF/dJds misaligned");
+    return CLBM_OK;
+}
+
+// The adjoint step with its dJ/ds partial sums in `partials` (one row per block) and, when there are more
+// rows than one reduction pass takes, their folded rows in `folded`.
+int adjoint_step_with(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, void *dJdF,
+                      double *dJds, double *partials, double *folded)
+{
     const unsigned nb = node_blocks(ctx);
     int rc = dispatch_d3q27(ctx, [&](auto v) {
         using Vt = decltype(v);
@@ -720,16 +721,15 @@ int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, 
                            static_cast<const S *>(state_t), ctx->geom, ctx->links,
                            static_cast<const R *>(ctx->d.force), make_forcing<R>(ctx->d), make_rates<R>(ctx->d.s),
                            static_cast<const R *>(lam_next), static_cast<R *>(lam_out), static_cast<R *>(dJdF),
-                           ctx->partials);
+                           partials);
         return check_launch(ctx, "adjoint kernel launch");
     });
     if (rc || !dJds) return rc;
-    const double *rows = ctx->partials;
+    const double *rows = partials;
     unsigned nrows = nb;
     if (nb > static_cast<unsigned>(kMaxBlocks)) {  // fold the long table first (fixed order)
-        double *folded = ctx->partials + partial_blocks(ctx) * kPartialStride;
         nrows = (nb + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_fold<kAdjRates>, dim3(nrows), dim3(kBlock), 0, ctx->stream, ctx->partials,
+        hipLaunchKernelGGL(k_fold<kAdjRates>, dim3(nrows), dim3(kBlock), 0, ctx->stream, partials,
                            static_cast<int>(nb), folded);
         rc = check_launch(ctx, "fold kernel launch");
         if (rc) return rc;
@@ -739,6 +739,21 @@ int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, 
                        kAdjRates, dJds + 2, 1);
     return check_launch(ctx, "reduce kernel launch");
 }
+
+}  // namespace
+
+extern "C" {
+
+int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, void *dJdF,
+                      double *dJds)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    const int rc = check_adjoint_args(ctx, state_t, lam_next, lam_out, dJdF, dJds);
+    if (rc) return rc;
+    return adjoint_step_with(ctx, state_t, lam_next, lam_out, dJdF, dJds, ctx->partials,
+                             ctx->partials + partial_blocks(ctx) * kPartialStride);
+}
+
 
 int clbm_loss_seed(clbm_ctx *ctx, const void *state, const void *u_target, void *lam_out, void *dJdF, double *J)
 {

@@ -535,14 +535,12 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
     return static_cast<uint32_t>(r < 0 ? r + static_cast<int>(n) : r);
 }
 
-// KEEP: also store the intermediate state (after step t+1) into `mid`, as a single step would have
-// written it; each tile stores its own nodes of its own planes, so every node is written once.
 // (the waves-per-EU bound keeps the register budget at or below 128)
-template <typename S, bool FIELD, int COLL, bool SOLID, bool KEEP>
+template <typename S, bool FIELD, int COLL, bool SOLID>
 __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) void k_step2(
-    const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ mid, Geom g, T2Geom tg,
-    const uint32_t *__restrict__ links, const typename Traits<S>::R *__restrict__ field,
-    Forcing<typename Traits<S>::R> fo, Rates<typename Traits<S>::R> rt)
+    const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const uint32_t *__restrict__ links,
+    const typename Traits<S>::R *__restrict__ field, Forcing<typename Traits<S>::R> fo,
+    Rates<typename Traits<S>::R> rt)
 {
     using R = typename Traits<S>::R;
     static_assert(std::is_same<R, float>::value, "the LDS ring holds FP32 values");
@@ -586,9 +584,6 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     const int hs = hy * kT2HX + hx;
     const bool ha = tid < kT2H;
     const uint32_t gx = wrap_coord(x0 - 1 + hx, g.nx), gy = wrap_coord(y0 - 1 + hy, g.ny);
-    // KEEP: this thread's first-step node belongs to the tile (not to its halo ring) and to the lattice
-    const bool own = hx >= 1 && hx <= kT2X && hy >= 1 && hy <= kT2Y && x0 - 1 + hx < static_cast<int>(g.nx) &&
-                     y0 - 1 + hy < static_cast<int>(g.ny);
     const int cx = tid % kT2X, cy = tid / kT2X;
     const bool ca = tid < kT2X * kT2Y && x0 + cx < static_cast<int>(g.nx) && y0 + cy < static_cast<int>(g.ny);
 
@@ -624,15 +619,6 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
         node_update<COLL>(v, Fx, Fy, Fz, rt);
-        if constexpr (KEEP) {
-            if (own && p >= z0 && p < z1) {
-                const uint32_t off = n * static_cast<uint32_t>(sizeof(S));
-                sfor<0, 27>([&](auto TT) {
-                    constexpr int t = decltype(TT)::value;
-                    store_at(mid + static_cast<size_t>(pop_of_slot(t)) * g.P, off, to_store<S>(v[t]));
-                });
-            }
-        }
         const int r0 = zm(p);
         sfor<0, 9>([&](auto J) {
             constexpr int j = decltype(J)::value;  // j = 3 a + b; slot 3 j + c with c = e_z + 1

@@ -70,8 +70,11 @@ def test_default_plane_stride():
 
 
 def test_strerror_and_version():
+    from paper_1801_04586_amd import clbm
+
     L = _lib()
-    assert L.clbm_abi_version() == 5
+    declared = int(re.search(r"#define CLBM_ABI_VERSION (\d+)", open(HEADER).read()).group(1))
+    assert L.clbm_abi_version() == declared == clbm.ABI_VERSION
     for code, word in [(0, b"success"), (1, b"invalid"), (2, b"rate"), (3, b"storage"), (4, b"HIP"),
                        (5, b"non-finite")]:
         assert word in L.clbm_strerror(code)
@@ -143,6 +146,7 @@ def test_calls_on_null_context_fail_cleanly():
     assert L.clbm_fused_pairs(None) == 1
     assert L.clbm_moments(None, None, None, None, None, None) == 1
     assert L.clbm_adjoint_step(None, None, None, None, None, None) == 1
+    assert L.clbm_trajectory(None, None, None, 2) == 1
     assert L.clbm_destroy(None) == 0
     assert L.clbm_set_rates(None, None) == 1
 
