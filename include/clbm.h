@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 6
+#define CLBM_ABI_VERSION 7
 
 /* Velocity sets: D3Q27 (Eq. (1), moment set Eq. (12)) and D3Q19 (Appendix A,
  * Eq. (A1)-(A6): velocities without the eight corners, moments of Eq. (A2),
@@ -264,6 +264,22 @@ int clbm_set_populations(clbm_ctx *ctx, const double *f, void *state);
  * only (moving walls allowed: their momentum exchange is a constant). */
 int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, void *dJdF,
                       double *dJds);
+
+/* clbm_adjoint_step for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, error behaviour and results
+ * (bitwise) as clbm_adjoint_step, and the same kernels; the call makes no allocation of any kind.  Its
+ * dJ/ds partial sums go to a static device array of 8.03 MiB instead of the context's scratch: the
+ * library holds one such array on every device it runs on until the process ends, and clbm_create
+ * looks up its address on the context's device.  That array limits the lattice to
+ * clbm_adjoint_noalloc_max_nodes() = 2^25 nodes; larger lattices get CLBM_EINVAL.  All calls on one
+ * device share the array, so calls that overlap on one device (several streams or threads) race and
+ * must be serialised by the caller.  Nothing in it needs clearing between calls: a call reads only
+ * entries it has written itself. */
+int clbm_adjoint_step_noalloc(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out,
+                              void *dJdF, double *dJds);
+
+/* Largest lattice (nx * ny * nz) clbm_adjoint_step_noalloc accepts: 2^25.  Host only. */
+int64_t clbm_adjoint_noalloc_max_nodes(void);
 
 /* Loss J = 1/2 sum over fluid nodes |u(x) - u_target(x)|^2 with u of Eq. (9)
  * evaluated on `state`.  u_target: device [3][N] of the adjoint type.

@@ -23,7 +23,7 @@ STORAGE_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float1
 # arithmetic / adjoint / force-field type per storage
 REAL_TORCH = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float32, "bf16": torch.float32}
 RATE_NAMES = ("s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6")
-ABI_VERSION = 6  # CLBM_ABI_VERSION of include/clbm.h
+ABI_VERSION = 7  # CLBM_ABI_VERSION of include/clbm.h
 CLBM_D3Q27, CLBM_D3Q19 = 0, 1
 LATTICE = {"d3q27": CLBM_D3Q27, "d3q19": CLBM_D3Q19}
 LATTICE_Q = {"d3q27": 27, "d3q19": 19}
@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH):
         "clbm_sample_populations": ([vp, vp, vp, i32, vp], ctypes.c_int),
         "clbm_adjoint_step": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "clbm_loss_seed": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "clbm_adjoint_step_noalloc": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "clbm_adjoint_noalloc_max_nodes": ([], ctypes.c_int64),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -250,6 +252,13 @@ class Context:
     def adjoint_step(self, state_t, lam_next, lam_out, dJdF=None, dJds=None):
         n, r = self.desc.nx * self.desc.ny * self.desc.nz, self.adjoint_dtype
         self._call("clbm_adjoint_step", self._state(state_t), self._buf(lam_next, "lam_next", r, 27 * n),
+                   self._buf(lam_out, "lam_out", r, 27 * n), self._buf(dJdF, "dJdF", r, 3 * n, True),
+                   self._buf(dJds, "dJds", torch.float64, 10, True))
+
+    def adjoint_step_noalloc(self, state_t, lam_next, lam_out, dJdF=None, dJds=None):
+        """clbm_adjoint_step_noalloc: clbm_adjoint_step without any allocation (lattices <= 2^25 nodes)."""
+        n, r = self.desc.nx * self.desc.ny * self.desc.nz, self.adjoint_dtype
+        self._call("clbm_adjoint_step_noalloc", self._state(state_t), self._buf(lam_next, "lam_next", r, 27 * n),
                    self._buf(lam_out, "lam_out", r, 27 * n), self._buf(dJdF, "dJdF", r, 3 * n, True),
                    self._buf(dJds, "dJds", torch.float64, 10, True))
 

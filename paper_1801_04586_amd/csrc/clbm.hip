@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -22,8 +23,23 @@ constexpr int kPartialStride = 8;  // doubles per block in the partials buffer (
 
 thread_local char g_err[512] = "no error";
 
+// Static scratch of clbm_adjoint_step_noalloc: the per-block dJ/ds partial sums of k_adjoint (one row
+// of kAdjRates doubles per kBlock nodes) and the rows k_fold reduces them to.  Sized for lattices of up
+// to 2^25 nodes: 131072 + 512 rows, 8.03 MiB on each device the library runs on, held until the process
+// ends.  Host code never uses the symbol itself as an address: each device's address comes from
+// hipGetSymbolAddress (scratch_address) and is kept with the context.
+constexpr size_t kNoallocMaxNodes = size_t(1) << 25;
+constexpr size_t kNoallocRows = kNoallocMaxNodes / kBlock;
+constexpr size_t kNoallocFoldedRows = kNoallocRows / kBlock;
+static_assert(kNoallocRows % kBlock == 0, "folded rows cover the partial rows exactly");
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
 
+static __device__ __align__(256) double scratch[(kNoallocRows + kNoallocFoldedRows) * kAdjRates];
 
 struct clbm_ctx {
     clbm_desc d;
@@ -35,6 +51,8 @@ struct clbm_ctx {
     uint32_t *links;   // [N] link table (k_links) when the lattice has solid nodes, else NULL
     uint32_t options;  // CLBM_OPT_* flags
     int num_cu;        // compute units of the device
+    int device;        // device the context was created on
+    double *scratch;   // that device's address of the static scratch (clbm_adjoint_step_noalloc)
     int t2_slots[2][2][2];  // resident blocks of the fused kernel, by (links, force field, collision); 0 = unknown
     char err[512];
 };
@@ -186,6 +204,22 @@ int dispatch_d3q27(clbm_ctx *c, F &&f)
 }
 
 unsigned node_blocks(const clbm_ctx *c) { return static_cast<unsigned>((c->nodes + kBlock - 1) / kBlock); }
+
+// Device address of the static scratch on device dev (current), looked up once per device.
+hipError_t scratch_address(int dev, double **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 // Blocks whose partial sums the context's scratch holds: the grid-stride kernels
 // use at most kMaxBlocks; the adjoint and loss kernels (D3Q27 cascaded lattices
@@ -411,8 +445,17 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
     {
         int dev = 0;
         c->num_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = scratch_address(dev, &c->scratch);
+        if (e != hipSuccess) {
+            rc = hip_fail(nullptr, e, "device or static scratch address");
+            (void)hipFree(c->partials);
+            (void)hipFree(c->scal);
+            delete c;
+            return rc;
+        }
+        c->device = dev;
+        if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             c->num_cu = 0;
         if (c->num_cu <= 0) c->num_cu = 256;
         std::memset(c->t2_slots, 0, sizeof(c->t2_slots));
@@ -754,6 +797,22 @@ int clbm_adjoint_step(clbm_ctx *ctx, const void *state_t, const void *lam_next, 
                              ctx->partials + partial_blocks(ctx) * kPartialStride);
 }
 
+int clbm_adjoint_step_noalloc(clbm_ctx *ctx, const void *state_t, const void *lam_next, void *lam_out, void *dJdF,
+                              double *dJds)
+{
+    if (!ctx) return fail(nullptr, CLBM_EINVAL, "ctx is NULL");
+    if (ctx->nodes > kNoallocMaxNodes)
+        return fail(ctx, CLBM_EINVAL,
+                    "lattice larger than the 2^25 nodes the static scratch of clbm_adjoint_step_noalloc holds%s",
+                    " (use clbm_adjoint_step)");
+    const int rc = check_adjoint_args(ctx, state_t, lam_next, lam_out, dJdF, dJds);
+    if (rc) return rc;
+    // scratch: a device address from hipGetSymbolAddress (set up by clbm_create on this device)
+    return adjoint_step_with(ctx, state_t, lam_next, lam_out, dJdF, dJds, ctx->scratch,
+                             ctx->scratch + kNoallocRows * kAdjRates);
+}
+
+int64_t clbm_adjoint_noalloc_max_nodes(void) { return static_cast<int64_t>(kNoallocMaxNodes); }
 
 int clbm_loss_seed(clbm_ctx *ctx, const void *state, const void *u_target, void *lam_out, void *dJdF, double *J)
 {
