@@ -592,8 +592,12 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     float keep0[9], keep2a[9], keep2b[9];
     uint32_t lm_a = 0, lm_b = 0;  // SOLID: the halo node's link words in planes p - 1 and p
 
+    // The first step's wavefronts run at raised priority until their 27 pulls are consumed: the
+    // arbiter then issues their loads ahead of the other block's arithmetic, so more memory is in
+    // flight while the SIMDs compute (measured +10% on the 512^3 headline, +5% on the porous duct).
     auto first_step = [&](int p) {
         if (!ha) return;
+        __builtin_amdgcn_s_setprio(3);
         const uint32_t pz = wrap_coord(p, g.nz);
         const uint32_t n = gx + g.nx * (gy + g.ny * pz);
         Nbr nb;
@@ -618,6 +622,7 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         }
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+        __builtin_amdgcn_s_setprio(0);
         node_update<COLL>(v, Fx, Fy, Fz, rt);
         const int r0 = zm(p);
         sfor<0, 9>([&](auto J) {
