@@ -460,6 +460,10 @@ __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src,
     Nbr nb;
     neighbours(g, n, nb);
     R v[27];
+    // FP32/FP16/BF16: raised wavefront priority until the pulls are consumed, as in the fused kernel
+    // (+2% to +5% on these storage types; FP64, whose node update is twice as long, lost 4% with it)
+    constexpr bool kPrio = !std::is_same<S, double>::value;
+    if constexpr (kPrio) __builtin_amdgcn_s_setprio(3);
     if (!SOLID || lm != 0u) {
         gather<S, CHECK, SOLID, false, Q>(src, g, n, nb, lm, v);
         if constexpr (!Traits<S>::kDev)
@@ -470,6 +474,7 @@ __device__ __forceinline__ void step_node(uint32_t n, const S *__restrict__ src,
 
     R Fx, Fy, Fz;
     force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+    if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
     node_update<COLL, Q>(v, Fx, Fy, Fz, rt);
 
     const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
