@@ -418,6 +418,10 @@ int clbm_create(clbm_ctx **out, const clbm_desc *desc, void *stream)
     g.P = desc->plane_stride ? static_cast<uint32_t>(desc->plane_stride) : g.N;
     g.dnx.init(g.nx);
     g.dny.init(g.ny);
+    // (a group wider than 2^31 rows means nz < kZGroup: one partial group, any divisor above the row count will do)
+    g.dzg.init(static_cast<uint32_t>(std::min<uint64_t>(uint64_t(kZGroup) * g.ny, 1ull << 31)));
+    g.dzr.init(g.nz % kZGroup ? g.nz % kZGroup : 1u);
+    g.zgroup = static_cast<uint64_t>(g.nx) * g.ny >= kZGroupMinPlane ? 1u : 0u;
     for (int a = 0; a < 3; ++a) g.wall[a] = desc->wall[a];
     g.moving = 0;
     for (int f = 0; f < 6; ++f)

@@ -34,7 +34,16 @@ def _case(dims, walls, seed, solid_frac):
 def test_adjoint_step_matches_oracle(walls, solid_frac, storage, tol):
     """One adjoint step against the oracle's exact discrete adjoint at the populations the kernel reads
     (the stored state, already rounded to the storage type); FP32 arithmetic for FP32/FP16/BF16."""
-    dims = (7, 6, 5)
+    _check_adjoint_step((7, 6, 5), walls, solid_frac, storage, tol)
+
+
+def test_adjoint_step_with_solids_on_large_planes():
+    """With solids and at least 98 304 nodes per plane the kernel visits nodes in groups of eight z
+    planes (here a whole group and a partial one)."""
+    _check_adjoint_step((320, 310, 10), (0, 1, 1), 0.2, "f64", 1e-12)
+
+
+def _check_adjoint_step(dims, walls, solid_frac, storage, tol):
     g, f0, field, solid = _case(dims, walls, 11, solid_frac)
     force = (1e-5, -2e-5, 5e-6)
     lat = _lattice(dims, walls, storage, force=force, field=field, solid=solid)

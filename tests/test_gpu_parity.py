@@ -123,6 +123,13 @@ def test_step_parity_f64_several_blocks_and_ragged_tail():
     assert _compare((23, 19, 13), (0, 0, 0), "f64", 6, 32, with_field=False) < TOL["f64"]
 
 
+@pytest.mark.parametrize("dims,walls", [((316, 312, 17), (0, 1, 1)), ((400, 250, 12), (1, 0, 0))])
+def test_step_parity_f64_solids_on_large_planes(dims, walls):
+    """With solids and at least 98 304 nodes per plane the step kernel visits nodes in groups of eight
+    z planes: two whole groups and a partial one, or one and a partial one."""
+    assert _compare(dims, walls, "f64", 2, 51, solid_frac=0.2) < TOL["f64"]
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("walls,solid_frac", [((0, 0, 0), 0.0), ((0, 1, 1), 0.0), ((1, 0, 1), 0.2)])
 def test_step_parity_reduced_storage_one_step(storage, walls, solid_frac):
