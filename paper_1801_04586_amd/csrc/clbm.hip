@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/clbm.h"
+#include "host_logic.hpp"
 #include "kernels.hpp"
 
 using namespace clbm;
@@ -21,7 +22,7 @@ namespace {
 constexpr int kMaxBlocks = 2048;   // grid of the grid-stride kernels (8 blocks per CU)
 constexpr int kPartialStride = 8;  // doubles per block in the partials buffer (>= kMomComp, kAdjRates)
 
-thread_local char g_err[512] = "no error";
+thread_local char g_err[clbm_host::kErrLen] = "no error";
 
 // Static scratch of clbm_adjoint_step_noalloc: the per-block dJ/ds partial sums of k_adjoint (one row
 // of kAdjRates doubles per kBlock nodes) and the rows k_fold reduces them to.  Sized for lattices of up
@@ -54,7 +55,7 @@ struct clbm_ctx {
     int device;        // device the context was created on
     double *scratch;   // that device's address of the static scratch (clbm_adjoint_step_noalloc)
     int t2_slots[2][2][2];  // resident blocks of the fused kernel, by (links, force field, collision); 0 = unknown
-    char err[512];
+    char err[clbm_host::kErrLen];
 };
 
 namespace {
@@ -62,14 +63,14 @@ namespace {
 int fail(clbm_ctx *c, int code, const char *fmt, const char *arg = "")
 {
     char *dst = c ? c->err : g_err;
-    std::snprintf(dst, 512, fmt, arg);
+    std::snprintf(dst, clbm_host::kErrLen, fmt, arg);
     return code;
 }
 
 int hip_fail(clbm_ctx *c, hipError_t e, const char *what)
 {
     char *dst = c ? c->err : g_err;
-    std::snprintf(dst, 512, "%s: %s", what, hipGetErrorString(e));
+    std::snprintf(dst, clbm_host::kErrLen, "%s: %s", what, hipGetErrorString(e));
     return CLBM_EHIP;
 }
 
@@ -79,60 +80,13 @@ int check_launch(clbm_ctx *c, const char *what)
     return e == hipSuccess ? CLBM_OK : hip_fail(c, e, what);
 }
 
-bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool aligned(const void *p) { return clbm_host::aligned16(p); }
 
-int validate_rates(clbm_ctx *c, const double *s)
-{
-    static const char *const names[10] = {"s0", "s1", "s2", "s2b", "s3", "s3b", "s4", "s4b", "s5", "s6"};
-    for (int k = 0; k < 10; ++k)
-        if (!(s[k] > 0.0 && s[k] < 2.0)) return fail(c, CLBM_ERATE, "relaxation rate %s outside (0, 2)", names[k]);
-    return CLBM_OK;
-}
+int validate_rates(clbm_ctx *c, const double *s) { return clbm_host::validate_rates(c ? c->err : g_err, s); }
 
-int validate_desc(const clbm_desc *d)
-{
-    if (!d) return fail(nullptr, CLBM_EINVAL, "desc is NULL");
-    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(nullptr, CLBM_EINVAL, "lattice dims must be >= 1");
-    const long long n = static_cast<long long>(d->nx) * d->ny * d->nz;
-    if (n >= (1ll << 31)) return fail(nullptr, CLBM_EINVAL, "nx*ny*nz must be below 2^31");
-    for (int a = 0; a < 3; ++a)
-        if (d->wall[a] != 0 && d->wall[a] != 1) return fail(nullptr, CLBM_EINVAL, "wall flags must be 0 or 1");
-    if (d->storage < CLBM_F64 || d->storage > CLBM_BF16) return fail(nullptr, CLBM_EDTYPE, "unknown storage type");
-    // kernels address a plane (state, adjoint, force field: elements of at most 8 bytes for FP64
-    // storage, 4 otherwise) with 32-bit byte offsets
-    const long long widest = d->storage == CLBM_F64 ? 8 : 4;
-    if (n * widest > (1ll << 32))
-        return fail(nullptr, CLBM_EINVAL, "lattice too large: nx*ny*nz times the element size must not exceed 4 GiB");
-    if (d->lattice != CLBM_D3Q27 && d->lattice != CLBM_D3Q19) return fail(nullptr, CLBM_EINVAL, "unknown lattice");
-    if (d->collision != CLBM_CASCADED && d->collision != CLBM_MRT)
-        return fail(nullptr, CLBM_EINVAL, "unknown collision model");
-    if (d->collision == CLBM_MRT && d->lattice != CLBM_D3Q27)
-        return fail(nullptr, CLBM_EINVAL, "the MRT collision needs the D3Q27 lattice");
-    if (d->reserved != 0) return fail(nullptr, CLBM_EINVAL, "reserved field must be 0");
-    if (d->plane_stride != 0) {
-        const size_t es = d->storage == CLBM_F64 ? 8 : (d->storage == CLBM_F32 ? 4 : 2);
-        if (d->plane_stride < n || d->plane_stride > 0xffffffffll)
-            return fail(nullptr, CLBM_EINVAL, "plane_stride must lie in [nx*ny*nz, 2^32)");
-        if ((static_cast<size_t>(d->plane_stride) * es) % 16 != 0)
-            return fail(nullptr, CLBM_EINVAL, "plane_stride * element size must be a multiple of 16 bytes");
-    }
-    for (int f = 0; f < 6; ++f)
-        for (int b = 0; b < 3; ++b) {
-            const double w = d->wall_velocity[f][b];
-            if (!std::isfinite(w)) return fail(nullptr, CLBM_EINVAL, "wall velocity not finite");
-            if (w != 0.0 && !d->wall[f / 2])
-                return fail(nullptr, CLBM_EINVAL, "a face of a periodic axis cannot move");
-        }
-    int rc = validate_rates(nullptr, d->s);
-    if (rc) return rc;
-    for (int a = 0; a < 3; ++a)
-        if (!std::isfinite(d->force_uniform[a])) return fail(nullptr, CLBM_EINVAL, "force_uniform not finite");
-    if (!std::isfinite(d->force_scale)) return fail(nullptr, CLBM_EINVAL, "force_scale not finite");
-    if (d->force && !aligned(d->force)) return fail(nullptr, CLBM_EINVAL, "force field not 16-byte aligned");
-    return CLBM_OK;
-}
+int validate_desc(const clbm_desc *d) { return clbm_host::validate_desc(d, g_err); }
 
-size_t store_size(int storage) { return storage == CLBM_F64 ? 8 : (storage == CLBM_F32 ? 4 : 2); }
+using clbm_host::store_size;
 int lattice_q(const clbm_desc &d) { return d.lattice == CLBM_D3Q19 ? 19 : 27; }
 
 template <typename R>
@@ -302,28 +256,7 @@ bool fused_pairs(const clbm_ctx *c)
     return tiles * chunks >= 2 * static_cast<uint64_t>(c->num_cu);
 }
 
-// A block of the fused kernel runs through a whole z chunk, so a launch whose last
-// round of blocks fills only part of the GPU idles for the rest of that round.
-// Choose the chunks per tile column (each of at least 8 planes) to minimise
-// rounds x (planes per chunk + 2), the two extra planes being the halo planes a
-// chunk recomputes; slots = blocks resident on the device at once.
-uint32_t fused_chunks(uint32_t tiles, uint32_t nz, uint32_t slots)
-{
-    const uint32_t max_chunks = nz / 8 > 1 ? nz / 8 : 1;
-    uint32_t best = 1;
-    unsigned long long best_cost = ~0ull;
-    for (uint32_t nc = 1; nc <= max_chunks; ++nc) {
-        const uint32_t zchunk = (nz + nc - 1) / nc;
-        const uint32_t used = (nz + zchunk - 1) / zchunk;
-        const unsigned long long rounds = (static_cast<unsigned long long>(tiles) * used + slots - 1) / slots;
-        const unsigned long long cost = rounds * (zchunk + 2);
-        if (cost < best_cost) {
-            best_cost = cost;
-            best = used;
-        }
-    }
-    return best;
-}
+using clbm_host::fused_chunks;
 
 int launch_step2(clbm_ctx *c, const void *src, void *dst)
 {
@@ -375,26 +308,10 @@ int clbm_abi_version(void) { return CLBM_ABI_VERSION; }
 
 int64_t clbm_default_plane_stride(int32_t nx, int32_t ny, int32_t nz, int32_t storage)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || storage < CLBM_F64 || storage > CLBM_BF16) return -1;
-    const long long n = static_cast<long long>(nx) * ny * nz;
-    if (n >= (1ll << 31)) return -1;
-    const long long es = static_cast<long long>(store_size(storage));
-    const long long align = 256 / es, pad = 4096 / es;
-    return (n + align - 1) / align * align + pad;
+    return clbm_host::default_plane_stride(nx, ny, nz, storage);
 }
 
-const char *clbm_strerror(int status)
-{
-    switch (status) {
-    case CLBM_OK: return "success";
-    case CLBM_EINVAL: return "invalid argument";
-    case CLBM_ERATE: return "relaxation rate outside (0, 2)";
-    case CLBM_EDTYPE: return "unknown storage type";
-    case CLBM_EHIP: return "HIP runtime error";
-    case CLBM_ENONFINITE: return "non-finite or non-positive density/velocity found";
-    default: return "unknown status";
-    }
-}
+const char *clbm_strerror(int status) { return clbm_host::status_string(status); }
 
 const char *clbm_last_error(const clbm_ctx *ctx) { return ctx ? ctx->err : g_err; }
 

@@ -67,6 +67,9 @@ def test_default_plane_stride():
     assert L.clbm_default_plane_stride(0, 6, 5, 1) == -1
     assert L.clbm_default_plane_stride(4, 4, 4, 9) == -1
     assert L.clbm_default_plane_stride(2048, 2048, 1024, 1) == -1
+    # products that overflow 64 bits (2^90 wraps to 0) are rejected, not wrapped
+    assert L.clbm_default_plane_stride(1 << 30, 1 << 30, 1 << 30, 1) == -1
+    assert L.clbm_default_plane_stride(1 << 30, 1 << 30, 16, 1) == -1
 
 
 def test_strerror_and_version():
@@ -102,6 +105,8 @@ def _desc(**kw):
 @pytest.mark.parametrize("kw,code,word", [
     (dict(dims=(0, 4, 4)), 1, "dims"),
     (dict(dims=(2048, 2048, 1024)), 1, "2^31"),
+    (dict(dims=(1 << 30, 1 << 30, 1 << 30), plane_stride=0), 1, "2^31"),
+    (dict(dims=(1 << 21, 1 << 21, 1 << 22), plane_stride=0), 1, "2^31"),
     (dict(walls=(0, 2, 0)), 1, "wall"),
     (dict(rates=[1.0, 1.0, 2.0] + [1.0] * 7), 2, "s2"),
     (dict(rates=[1.0, 1.0, 1.5, 1.0, 0.0] + [1.0] * 5), 2, "s3"),
