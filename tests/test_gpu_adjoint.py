@@ -262,7 +262,11 @@ def test_checkpoint_and_recompute_are_bitwise_equal_to_storing_every_state():
 
 
 def test_flow_loss_gradient_matches_central_differences_fp64():
-    """dJ/dF (random direction) and dJ/ds_k against central differences, eps = 1e-4 relative, FP64."""
+    """dJ/dF (random direction) against a central difference (eps = 1e-4 relative) and every dJ/ds_k
+    against central differences with steps of 1% and 0.5% of s_k combined by Richardson extrapolation,
+    FP64.  With steps of 1e-4 the rounding of J limits the smaller rate derivatives to about 1e-4
+    relative; the larger steps with the O(h^2) term cancelled agree with the exact discrete adjoint of
+    the oracle to 3e-6 relative or better for every rate on this case."""
     from paper_1801_04586_amd.adjoint import flow_loss
 
     dims, T = (10, 12, 6), 40
@@ -281,15 +285,18 @@ def test_flow_loss_gradient_matches_central_differences_fp64():
     v = np.random.default_rng(3).normal(0, 1, F.shape)
     eps = 1e-4 * np.max(np.abs(F))
     fd = (Jof(F + eps * v, rates) - Jof(F - eps * v, rates)) / (2 * eps)
-    assert abs(fd - np.sum(gF * v)) <= 1e-6 * abs(fd)
-    for k in (2, 3, 4, 6, 9):
+    assert abs(fd - np.sum(gF * v)) <= 1e-7 * abs(fd)
+
+    def central(k, h):
         sp, sm = rates.copy(), rates.copy()
-        h = 1e-4 * rates[k]
         sp[k] += h
         sm[k] -= h
-        fd = (Jof(F, sp) - Jof(F, sm)) / (2 * h)
-        # truncation of the O(h^2) difference dominates for derivatives far below the largest one
-        assert abs(fd - gs[k]) <= 1e-5 * abs(fd) + 1e-7 * np.max(np.abs(gs)), (k, fd, gs[k])
+        return (Jof(F, sp) - Jof(F, sm)) / (2 * h)
+
+    for k in range(2, 10):
+        h = 1e-2 * rates[k]
+        rich = (4 * central(k, h / 2) - central(k, h)) / 3
+        assert abs(rich - gs[k]) <= 2e-5 * abs(rich), (k, rich, gs[k])
     assert gs[0] == 0.0 and gs[1] == 0.0
     lat.close()
 
