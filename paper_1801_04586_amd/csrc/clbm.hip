@@ -515,14 +515,17 @@ int clbm_trajectory(clbm_ctx *ctx, const void *src, void *const *states, int32_t
     if (!src || !aligned(src)) return fail(ctx, CLBM_EINVAL, "src NULL or misaligned");
     if (nsteps == 0) return CLBM_OK;
     if (!states) return fail(ctx, CLBM_EINVAL, "states is NULL");
-    // every buffer distinct: a launch reads one of them while writing one or two others
-    std::vector<uintptr_t> seen;
-    seen.reserve(static_cast<size_t>(nsteps) + 1);
-    seen.push_back(reinterpret_cast<uintptr_t>(src));
-    for (int32_t k = 0; k < nsteps; ++k) {
+    // every buffer distinct: a launch reads one of them while writing another
+    for (int32_t k = 0; k < nsteps; ++k)
         if (!states[k] || !aligned(states[k])) return fail(ctx, CLBM_EINVAL, "a state buffer is NULL or misaligned");
-        seen.push_back(reinterpret_cast<uintptr_t>(states[k]));
+    std::vector<uintptr_t> seen;
+    try {
+        seen.reserve(static_cast<size_t>(nsteps) + 1);
+    } catch (...) {  // no exception crosses the C ABI
+        return fail(ctx, CLBM_EINVAL, "out of host memory");
     }
+    seen.push_back(reinterpret_cast<uintptr_t>(src));
+    for (int32_t k = 0; k < nsteps; ++k) seen.push_back(reinterpret_cast<uintptr_t>(states[k]));
     std::sort(seen.begin(), seen.end());
     if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
         return fail(ctx, CLBM_EINVAL, "src and the state buffers must be distinct");
