@@ -100,6 +100,13 @@ def test_step_parity_f64_several_blocks_and_ragged_tail():
     assert _compare((23, 19, 13), (0, 0, 0), "f64", 6, 32, with_field=False) < TOL["f64"]
 
 
+@pytest.mark.parametrize("storage,steps", [("f64", 2), ("f16", 1)])
+def test_step_parity_with_solids_on_large_planes(storage, steps):
+    """At least 98 304 nodes per plane with solids: nodes visited in groups of eight z planes (a whole
+    group and a partial one)."""
+    assert _compare((320, 310, 11), (0, 1, 1), storage, steps, 61, solid_frac=0.2) < TOL[storage]
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("walls,solid_frac", [((0, 0, 0), 0.0), ((0, 1, 1), 0.0), ((1, 0, 1), 0.2)])
 def test_step_parity_reduced_storage_one_step(storage, walls, solid_frac):
