@@ -737,7 +737,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--size", type=int, default=512, help="edge of the cubic Kolmogorov lattice")
-    ap.add_argument("--only", default="", help="comma-separated variant names (or 'headline'); no headline line")
+    ap.add_argument("--only", default="", help="comma-separated variant names (or 'headline'); no headline line. "
+                    "Variants: " + ", ".join(VARIANTS))
     ap.add_argument("--primary-only", action="store_true", help="time only the FP32 step (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true", help="also run the plain copy kernel (PMC scale)")
     ap.add_argument("--no-variants", action="store_true")
