@@ -6,9 +6,12 @@
 * Taylor-Green 128^3: kinetic-energy decay rate, FP32 vs FP64 velocity error,
   and oracle parity at sampled nodes (windows covering each node's light cone).
 * Kolmogorov 512^3 (FP32 with per-node force field, the benchmark's launch
-  configuration): sampled parity and the linear spin-up of the forced mode.
+  configuration): sampled parity and the linear spin-up of the forced mode;
+  sampled parity of the FP64, FP16 and BF16 single-step kernels; storage errors
+  against FP64.
 * Porous duct 640x320x320 (FP32, spheres, walls in y and z): sampled parity
-  next to solids, mass conservation.
+  next to solids, mass conservation, and sampled parity of one adjoint step on
+  the duct and on its 256x128x128 crop.
 """
 from __future__ import annotations
 
@@ -197,6 +200,29 @@ def test_kolmogorov_512_sampled_parity_fp32(kolmogorov_inputs):
     lat.close()
 
 
+@pytest.mark.parametrize("storage,tol", [("f64", 5e-15), ("f16", 1e-6), ("bf16", 5e-6)])
+def test_kolmogorov_512_sampled_parity_single_step_storages(storage, tol, kolmogorov_inputs):
+    """The single-step kernels the benchmark times for FP64, FP16 and BF16 storage at 512^3 (two steps)
+    against the oracle on the light cones of sampled nodes.  The oracle starts from the exact
+    equilibrium, the GPU from its storage-rounded deviations, so the bound is a few roundings of
+    deviations of order 1e-3 in the storage type (measured 5e-16, 1.1e-7 and 7e-7)."""
+    cfg = workloads.KOLMOGOROV512
+    u0, F = kolmogorov_inputs
+    k = 2
+    lat = _lattice(cfg.dims, cfg.walls, storage, cfg.rates(), field=F)
+    assert not lat.uses_fused_pairs
+    lat.init(None, u0)
+    lat.step(k)
+    samples = _samples(cfg.dims, 8, 13, include=[(0, 0, 0), (511, 511, 511), (17, 400, 256)])
+    Fs = lat.force_field.double().cpu().numpy()
+    err = _cone_parity(lat, cfg.dims, cfg.walls, cfg.rates(), k, samples, None, u0, field=Fs)
+    print(f"Kolmogorov 512^3 {storage} storage, {k} single steps: max |f - f_oracle| over the samples {err:.2e}")
+    assert err < tol, err
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
 def test_kolmogorov_512_linear_spinup_fp32(kolmogorov_inputs):
     cfg = workloads.KOLMOGOROV512
     u0, F = kolmogorov_inputs
@@ -291,4 +317,71 @@ def test_porous_duct_mass_conservation_and_flow(porous_mask):
     assert nbad == 0
     assert abs(tot[0] - m0) <= 1e-9 * m0
     assert tot[1] > 0 and abs(tot[2]) < 0.1 * tot[1] and abs(tot[3]) < 0.1 * tot[1]
+    lat.close()
+
+
+@pytest.mark.parametrize("which", ["crop_256x128x128", "full_640x320x320"])
+def test_porous_adjoint_step_sampled_parity(which, porous_mask):
+    """One adjoint step on the benchmark's porous lattices (FP32, per-node force field; the full duct
+    takes the z-grouped node order) against the oracle's exact adjoint on 3x3x3 windows around sampled
+    fluid nodes next to solids, walls and corners: lambda(t) and dJ/dF at a node depend only on its
+    own populations and on lambda(t+1) of its neighbours, so a window gives them exactly."""
+    cfg = workloads.POROUS
+    walls, rates = cfg.walls, cfg.rates()
+    if which.startswith("full"):
+        dims, mask = cfg.dims, porous_mask
+    else:
+        dims = (256, 128, 128)
+        mask = workloads.porous_spheres(dims, walls, 6.0, 12.0, 0.2, workloads.SEED)[0]
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    lat = _lattice(dims, walls, "f32", rates, force=cfg.force_uniform, field=workloads.gaussian_force(dims, 1e-6, 9),
+                   solid=mask)
+    lat.init(None, workloads.uniform_random_velocity(dims, 1e-3, 5))
+    lat.step(3)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    lam = torch.randn((27, n), device="cuda", generator=gen)
+    lam_out = torch.empty_like(lam)
+    gF = torch.zeros((3, n), device="cuda")
+    gs = torch.zeros(10, dtype=torch.float64, device="cuda")
+    lat.ctx.adjoint_step(lat.state, lam, lam_out, gF, gs)
+    torch.cuda.synchronize()
+
+    rng = np.random.default_rng(4)
+    zs, ys, xs = np.nonzero(mask[1:-1, 1:-1, 1:-1] == 0)
+    near = []
+    for p in rng.choice(len(xs), 4000, replace=False):
+        x, y, z = int(xs[p]) + 1, int(ys[p]) + 1, int(zs[p]) + 1
+        if mask[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].any():
+            near.append((x, y, z))
+        if len(near) == 8:
+            break
+    samples = near + [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (5, 0, nz // 2), (nx // 3, ny // 2, nz - 1)]
+    samples = [c for c in samples if mask[c[2], c[1], c[0]] == 0]
+    assert len(samples) >= 8
+    field = lat.force_field.double().cpu().numpy()
+    got_lam, got_gF, ref_lam, ref_gF = [], [], [], []
+    for c in samples:
+        o, w, (ix, iy, iz) = _window(dims, walls, c, 1)
+        ids = (ix[None, None, :] + nx * (iy[None, :, None] + ny * iz[:, None, None])).ravel()
+        nodes = [(int(i % nx), int(i // nx % ny), int(i // (nx * ny))) for i in ids]
+        shape = (len(iz), len(iy), len(ix))
+        f = lat.sample(nodes).reshape((27,) + shape)
+        lw = lam[:, torch.from_numpy(ids).cuda()].double().cpu().numpy().reshape((27,) + shape)
+        sub = lambda a: np.ascontiguousarray(a[..., iz[:, None, None], iy[None, :, None], ix[None, None, :]])
+        gwin = oracle.Geometry(dims, walls, o, w)
+        rl, rF, _ = oracle.adjoint_step(gwin, f, lw, rates, force=cfg.force_uniform, force_field=sub(field),
+                                        solid=sub(mask))
+        k = (c[2] - o[2], c[1] - o[1], c[0] - o[0])
+        ref_lam.append(rl[(slice(None),) + k])
+        ref_gF.append(rF[(slice(None),) + k])
+        i = c[0] + nx * (c[1] + ny * c[2])
+        got_lam.append(lam_out[:, i].double().cpu().numpy())
+        got_gF.append(gF[:, i].double().cpu().numpy())
+    ref_lam, got_lam, ref_gF, got_gF = map(np.array, (ref_lam, got_lam, ref_gF, got_gF))
+    err_lam = np.max(np.abs(got_lam - ref_lam)) / np.max(np.abs(ref_lam))
+    err_gF = np.max(np.abs(got_gF - ref_gF)) / np.max(np.abs(ref_gF))
+    print(f"porous adjoint {which}: {len(samples)} sampled nodes, lambda rel {err_lam:.2e}, dJ/dF rel {err_gF:.2e}")
+    # FP32 arithmetic against FP64: measured below 4e-7 relative on both lattices
+    assert err_lam < 2e-6 and err_gF < 2e-6, (err_lam, err_gF)
     lat.close()
