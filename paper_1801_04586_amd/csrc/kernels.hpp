@@ -599,29 +599,40 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     // Halo position (hx, hy) of this thread in step t+1 and its LDS index hs = hy * kT2HX + hx.
     // Without solids: row-major (hs = tid); step t+2 of tile node (cx, cy) runs on thread
     // cy * kT2X + cx.  With solids, step t+2 of a tile node must run on the thread that stepped
-    // it in t+1 (its registers hold the node's own values), so threads 0 ... 383 take the tile
-    // nodes row by row and 384 ... 475 the halo ring: rows hy = 0 and 13, then columns hx = 0 and 33.
-    int hx, hy;
+    // it in t+1 (its registers hold the node's own values), so threads 0 ... 383 (wavefronts 0-5)
+    // take the tile nodes row by row.  The 92 halo-ring nodes go to wavefronts 6 and 7, each
+    // taking one whole halo row (34 nodes, corners included; coalesced) and the 12 column nodes
+    // of one side.  A column node is alone in its row, so each of its loads touches a cache line
+    // of its own; split over two wavefronts, those lines cost each wavefront's loads half as much,
+    // and the wavefronts that wait for the slowest at the plane barrier wait less.
+    int hx = 0, hy = 0;
+    bool ha;
     if constexpr (SOLID) {
-        constexpr int kCore = kT2X * kT2Y, kRows = 2 * kT2X;
+        constexpr int kCore = kT2X * kT2Y;
+        static_assert(kCore % 64 == 0 && kCore + 128 == kT2Block && kT2HX + kT2Y <= 64,
+                      "tile rows fill wavefronts 0-5 and the halo ring fits wavefronts 6 and 7");
+        ha = true;
         if (tid < kCore) {
             hx = 1 + tid % kT2X;
             hy = 1 + tid / kT2X;
-        } else if (tid < kCore + kRows) {
-            const int r = tid - kCore;
-            hx = 1 + r % kT2X;
-            hy = r < kT2X ? 0 : kT2HY - 1;
         } else {
-            const int r = tid - kCore - kRows;
-            hx = r < kT2HY ? 0 : kT2HX - 1;
-            hy = r % kT2HY;
+            const int side = (tid - kCore) >> 6, l = (tid - kCore) & 63;
+            if (l < kT2HX) {
+                hx = l;
+                hy = side ? kT2HY - 1 : 0;
+            } else if (l < kT2HX + kT2Y) {
+                hx = side ? kT2HX - 1 : 0;
+                hy = 1 + (l - kT2HX);
+            } else {
+                ha = false;  // 18 idle lanes in each of the two halo wavefronts
+            }
         }
     } else {
         hx = tid % kT2HX;
         hy = tid / kT2HX;
+        ha = tid < kT2H;
     }
     const int hs = hy * kT2HX + hx;
-    const bool ha = tid < kT2H;
     const uint32_t gx = wrap_coord(x0 - 1 + hx, g.nx), gy = wrap_coord(y0 - 1 + hy, g.ny);
     const int cx = tid % kT2X, cy = tid / kT2X;
     const bool ca = tid < kT2X * kT2Y && x0 + cx < static_cast<int>(g.nx) && y0 + cy < static_cast<int>(g.ny);
@@ -630,6 +641,12 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     // them: e_z = 0 of plane p, e_z = +1 of planes p - 1 and p (p: the last plane computed)
     float keep0[9], keep2a[9], keep2b[9];
     uint32_t lm_a = 0, lm_b = 0;  // SOLID: the halo node's link words in planes p - 1 and p
+    // SOLID: the link word of the next plane, loaded one plane ahead.  The checked pulls need it
+    // for their addresses, so loading it with them would put a second HBM round trip on the path
+    // of every plane.
+    uint32_t lm_next = 0;
+    if constexpr (SOLID)
+        if (ha) lm_next = links[gx + g.nx * (gy + g.ny * wrap_coord(z0 - 1, g.nz))];
 
     // The first step's wavefronts run at raised priority until their 27 pulls are consumed: the
     // arbiter then issues their loads ahead of the other block's arithmetic, so more memory is in
@@ -644,7 +661,8 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         constexpr uint32_t es = sizeof(S);
         R v[27];
         if constexpr (SOLID) {
-            const uint32_t lm = links[n];
+            const uint32_t lm = lm_next;
+            lm_next = links[gx + g.nx * (gy + g.ny * wrap_coord(p + 1, g.nz))];
             lm_a = lm_b;
             lm_b = lm;
             if (lm != 0u)
@@ -672,6 +690,18 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             keep2b[j] = static_cast<float>(to_store<S>(v[3 * j + 2]));
         });
     };
+
+    // Without solids, the force-field values of the second step are loaded one plane ahead, so
+    // that the node update does not wait for them (the first step's loads carry its own).  The
+    // link-table variant has no registers to spare for them.
+    constexpr bool kFieldAhead = FIELD && !SOLID;
+    auto tile_node = [&](int z) {
+        return static_cast<uint32_t>(x0 + cx) +
+               g.nx * (static_cast<uint32_t>(y0 + cy) + g.ny * wrap_coord(z, g.nz));
+    };
+    R fnx = R(0), fny = R(0), fnz = R(0);
+    if constexpr (kFieldAhead)
+        if (ca) load_field<FIELD>(field, g.N, tile_node(z0), fnx, fny, fnz);
 
     auto second_step = [&](int z) {
         if (!ca) return;
@@ -727,7 +757,12 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = rf[pulled_at(TT)]; });
         }
         R Fx, Fy, Fz;
-        force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+        if constexpr (kFieldAhead) {
+            force_from<FIELD>(fo, fnx, fny, fnz, Fx, Fy, Fz);
+            load_field<FIELD>(field, g.N, tile_node(z + 1), fnx, fny, fnz);
+        } else {
+            force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
+        }
         node_update<COLL>(v, Fx, Fy, Fz, rt);
         const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
         sfor<0, 27>([&](auto TT) {
