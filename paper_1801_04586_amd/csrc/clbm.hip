@@ -272,11 +272,12 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         constexpr bool SOLID = decltype(solid_tag)::value;
         auto launch = [&](auto cc) {
             constexpr int C = decltype(cc)::value;
+            constexpr unsigned dyn_lds = SOLID ? 0u : kT2PadLds;
             int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0];
             if (slots == 0) {
                 int per_cu = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID>, kT2Block,
-                                                                 0) != hipSuccess ||
+                                                                 dyn_lds) != hipSuccess ||
                     per_cu < 1)
                     per_cu = 1;
                 slots = per_cu * c->num_cu;
@@ -285,7 +286,7 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
             tg.zchunk = (c->geom.nz + nchunks_req - 1) / nchunks_req;
             const uint32_t nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
             const unsigned blocks = tiles * nchunks;
-            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID>), dim3(blocks), dim3(kT2Block), 0, c->stream,
+            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID>), dim3(blocks), dim3(kT2Block), dyn_lds, c->stream,
                                static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg, c->links,
                                static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
             return check_launch(c, "fused two-step kernel launch");

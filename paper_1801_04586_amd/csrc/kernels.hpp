@@ -560,9 +560,44 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 // node's e_z = +1 group and link word; the e_z = 0 group of plane z is in LDS,
 // and the e_z = -1 groups alternate between two LDS slots by plane parity so
 // that plane z's stays readable while plane z+1's is written (68.5 KB per block).
+// Population i's slot (inverse of pop_of_slot).
+__host__ __device__ constexpr int slot_of_pop(int i)
+{
+    for (int t = 0; t < 27; ++t)
+        if (pop_of_slot(t) == i) return t;
+    return -1;
+}
+
+// Address of population plane i + 1 from that of plane i, for loops over the planes in
+// increasing order inside the fused kernel's plane loop.  Left to itself the compiler
+// keeps all 27 source and 27 destination plane addresses live across that loop (108
+// scalar registers): they do not fit beside the rest of the kernel's uniform state, so
+// they are spilled to vector lanes and each reload costs two vector instructions on
+// every load and store.  The empty asm makes the running byte offset opaque, so each
+// address is formed by scalar adds where it is used.  The asm orders the accesses
+// between which it sits: stores forced into plane order wait for the end of the node
+// update (the values come out in slot order) and hold the next plane's loads back
+// behind them in the in-order memory counter, so the periodic variant, whose 27
+// destination addresses then fit, stores in slot order.  (The offset, not the address,
+// goes through the asm: an address derived from the kernel argument by arithmetic
+// keeps its global address space, and the accesses keep their scalar-base form.)
+template <typename T>
+__device__ __forceinline__ T *next_plane(T *base, uint64_t &off, uint64_t stride_bytes)
+{
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    off += stride_bytes;
+    asm volatile("" : "+s"(off));
+    return reinterpret_cast<T *>(reinterpret_cast<B *>(base) + off);
+}
+
 constexpr int kT2X = 32, kT2Y = 12;
 constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 476 nodes
 constexpr int kT2Block = (kT2H + 63) / 64 * 64;                             // 512 threads, eight wavefronts
+// Dynamic LDS requested with each launch of the variant without a link table: it keeps that
+// kernel at two blocks per CU.  Its 51 KB ring alone would let a third block in whenever
+// the kernel needs 80 VGPRs or fewer, and three blocks per CU ran the 512^3 lattice 27%
+// slower.  (The link-table variant's 68.5 KB ring already admits only two.)
+constexpr unsigned kT2PadLds = 4096;
 
 struct T2Geom {
     uint32_t tiles_x, tiles_y, zchunk;
@@ -637,6 +672,7 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     const int cx = tid % kT2X, cy = tid / kT2X;
     const bool ca = tid < kT2X * kT2Y && x0 + cx < static_cast<int>(g.nx) && y0 + cy < static_cast<int>(g.ny);
 
+    const uint64_t plane_bytes = static_cast<uint64_t>(g.P) * sizeof(S);
     // groups of the halo node's intermediate values kept in registers until the plane that pulls
     // them: e_z = 0 of plane p, e_z = +1 of planes p - 1 and p (p: the last plane computed)
     float keep0[9], keep2a[9], keep2b[9];
@@ -670,11 +706,14 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             else
                 sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });  // solid: the rest state, as step_node
         } else {
-            sfor<0, 27>([&](auto TT) {
-                constexpr int t = decltype(TT)::value;
+            const S *__restrict__ pl = src;  // plane i, planes in increasing order
+            uint64_t po = 0;
+            sfor<0, 27>([&](auto II) {
+                constexpr int i = decltype(II)::value, t = slot_of_pop(i);
                 uint32_t off;
                 link_open<t, false, false>(nb, 0u, off);
-                v[t] = to_real(load_at(src + static_cast<size_t>(pop_of_slot(t)) * g.P, off * es));
+                v[t] = to_real(load_at(pl, off * es));
+                if constexpr (i < 26) pl = next_plane(src, po, plane_bytes);
             });
         }
         R Fx, Fy, Fz;
@@ -765,10 +804,23 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         }
         node_update<COLL>(v, Fx, Fy, Fz, rt);
         const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
-        sfor<0, 27>([&](auto TT) {
-            constexpr int t = decltype(TT)::value;
-            store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.P, nb_off, to_store<S>(v[t]));
-        });
+        if constexpr (SOLID) {
+            // the link-table variant holds too many uniform values to keep the 27 destination
+            // plane addresses as well: stores in plane order with the running offset (measured
+            // +2% on the porous duct; the periodic variant has the registers and lost with it)
+            S *__restrict__ pl = dst;
+            uint64_t po = 0;
+            sfor<0, 27>([&](auto II) {
+                constexpr int i = decltype(II)::value, t = slot_of_pop(i);
+                store_at(pl, nb_off, to_store<S>(v[t]));
+                if constexpr (i < 26) pl = next_plane(dst, po, plane_bytes);
+            });
+        } else {
+            sfor<0, 27>([&](auto TT) {
+                constexpr int t = decltype(TT)::value;
+                store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.P, nb_off, to_store<S>(v[t]));
+            });
+        }
     };
 
     sfor<0, 9>([&](auto J) { keep2b[decltype(J)::value] = 0.0f; });
