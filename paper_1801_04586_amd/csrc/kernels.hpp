@@ -701,10 +701,44 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             lm_next = links[gx + g.nx * (gy + g.ny * wrap_coord(p + 1, g.nz))];
             lm_a = lm_b;
             lm_b = lm;
-            if (lm != 0u)
-                gather<S, true, true, false>(src, g, n, nb, lm, v);
-            else
+            if (lm == 0u) {
                 sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });  // solid: the rest state, as step_node
+            } else if (__all(lm == all_links<27>())) {
+                const S *__restrict__ pl = src;  // plane i, planes in increasing order
+                uint64_t po = 0;
+                sfor<0, 27>([&](auto II) {
+                    constexpr int i = decltype(II)::value, t = slot_of_pop(i);
+                    uint32_t off;
+                    link_open<t, false, false>(nb, 0u, off);
+                    v[t] = to_real(load_at(pl, off * es));
+                    if constexpr (i < 26) pl = next_plane(src, po, plane_bytes);
+                });
+            } else {
+                // the gather of Eq. (8) with its checks, planes in increasing order: a blocked
+                // link takes the node's own opposite population (plane ib), whose address is an
+                // opaque multiple of the plane stride, formed in scalar registers where it is used
+                const bool mf = g.moving && on_moving_face(g, nb);
+                const S *__restrict__ pl = src;
+                uint64_t po = 0;
+                sfor<0, 27>([&](auto II) {
+                    constexpr int i = decltype(II)::value, t = slot_of_pop(i);
+                    if constexpr (t == 13) {
+                        v[t] = to_real(load_at(pl, n * es));
+                    } else {
+                        constexpr int ib = pop_of_slot(26 - t);
+                        uint32_t off;
+                        const bool ok = link_open<t, false, true>(nb, lm, off);
+                        uint64_t pb = plane_bytes;
+                        asm volatile("" : "+s"(pb));
+                        const S *__restrict__ own =
+                            reinterpret_cast<const S *>(reinterpret_cast<const char *>(src) + pb * ib);
+                        const S val = ok ? load_at(pl, off * es) : load_at(own, n * es);
+                        v[t] = to_real(val);
+                        if (mf && !ok) v[t] += wall_term<t, 27, R>(nb, g);
+                    }
+                    if constexpr (i < 26) pl = next_plane(src, po, plane_bytes);
+                });
+            }
         } else {
             const S *__restrict__ pl = src;  // plane i, planes in increasing order
             uint64_t po = 0;
