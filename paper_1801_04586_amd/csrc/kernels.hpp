@@ -574,11 +574,10 @@ __host__ __device__ constexpr int slot_of_pop(int i)
 // scalar registers): they do not fit beside the rest of the kernel's uniform state, so
 // they are spilled to vector lanes and each reload costs two vector instructions on
 // every load and store.  The empty asm makes the running byte offset opaque, so each
-// address is formed by scalar adds where it is used.  The asm orders the accesses
-// between which it sits: stores forced into plane order wait for the end of the node
-// update (the values come out in slot order) and hold the next plane's loads back
-// behind them in the in-order memory counter, so the periodic variant, whose 27
-// destination addresses then fit, stores in slot order.  (The offset, not the address,
+// address is formed by scalar adds where it is used.  The first-step loads use it in
+// both variants; the link-table variant also stores this way, while the periodic
+// variant, whose 27 destination addresses fit once the loads no longer hold 27 more,
+// keeps its stores in slot order.  (The offset, not the address,
 // goes through the asm: an address derived from the kernel argument by arithmetic
 // keeps its global address space, and the accesses keep their scalar-base form.)
 template <typename T>
@@ -840,8 +839,7 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
         if constexpr (SOLID) {
             // the link-table variant holds too many uniform values to keep the 27 destination
-            // plane addresses as well: stores in plane order with the running offset (measured
-            // +2% on the porous duct; the periodic variant has the registers and lost with it)
+            // plane addresses as well: stores in plane order with the running offset
             S *__restrict__ pl = dst;
             uint64_t po = 0;
             sfor<0, 27>([&](auto II) {
