@@ -198,8 +198,9 @@ int clbm_step(clbm_ctx *ctx, const void *src, void *dst);
 
 /* nsteps steps from the state in a, using a and b as the two buffers; the
  * buffer that holds the final state is returned in *result (host, may be
- * NULL).  On D3Q27 lattices with FP32 storage and the cascaded collision
- * (any walls, moving or not, and solid nodes), pairs of steps run as one fused
+ * NULL).  On D3Q27 lattices with FP32 storage, with the cascaded collision or
+ * the MRT of Appendix B (any walls, moving or not, and solid nodes), pairs of
+ * steps run as one fused
  * launch that keeps the intermediate state on chip (bitwise the same result as
  * two clbm_step calls) when the lattice fills the device: its 32 x 12 (x, y)
  * tile columns times z chunks of 8 planes give at least two blocks per compute

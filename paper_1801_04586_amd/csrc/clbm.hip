@@ -54,7 +54,7 @@ struct clbm_ctx {
     int num_cu;        // compute units of the device
     int device;        // device the context was created on
     double *scratch;   // that device's address of the static scratch (clbm_adjoint_step_noalloc)
-    int t2_slots[2][2][2];  // resident blocks of the fused kernel, by (links, force field, collision); 0 = unknown
+    int t2_slots[2][2][3];  // resident blocks of the fused kernel, by (links, force field, collision); 0 = unknown
     char err[clbm_host::kErrLen];
 };
 
@@ -239,7 +239,7 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
 // leaves the fused kernel two blocks per CU, slower than single steps.
 bool fused_kind(const clbm_desc &d)
 {
-    return d.lattice == CLBM_D3Q27 && d.storage == CLBM_F32 && d.collision == CLBM_CASCADED;
+    return d.lattice == CLBM_D3Q27 && d.storage == CLBM_F32;
 }
 
 // A lattice too small to give the fused kernel two blocks per compute unit (tile
@@ -273,7 +273,7 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         auto launch = [&](auto cc) {
             constexpr int C = decltype(cc)::value;
             constexpr unsigned dyn_lds = SOLID ? 0u : kT2PadLds;
-            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C == kCascadedHigh1 ? 1 : 0];
+            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C];
             if (slots == 0) {
                 int per_cu = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID>, kT2Block,
@@ -292,6 +292,7 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
             return check_launch(c, "fused two-step kernel launch");
         };
         if (coll == kCascadedHigh1) return launch(std::integral_constant<int, kCascadedHigh1>{});
+        if (coll == kMrt) return launch(std::integral_constant<int, kMrt>{});
         return launch(std::integral_constant<int, kCascaded>{});
     };
     if (c->links)

@@ -1,5 +1,5 @@
-"""Fused two-step launches (clbm_run on FP32 cascaded D3Q27 lattices: periodic,
-walled, moving walls, solid nodes) are bitwise identical to single steps,
+"""Fused two-step launches (clbm_run on FP32 D3Q27 lattices with the cascaded or the
+MRT collision: periodic, walled, moving walls, solid nodes) are bitwise identical to single steps,
 across ragged tiles, thin lattices, odd step counts, both collision paths, with
 or without a force field, every wall combination, random solids and packed
 spheres; and they match the oracle."""
@@ -76,7 +76,9 @@ def test_fused_pairs_apply_to_fp32_cascaded_d3q27_lattices():
              ("f32", (0, 1, 0), sol, lid, "d3q27", "cascaded", True),
              ("f32", (1, 1, 1), None, lid, "d3q27", "cascaded", True),
              ("f32", (0, 1, 0), None, None, "d3q19", "cascaded", False),
-             ("f32", (0, 1, 0), None, None, "d3q27", "mrt", False)]
+             ("f32", (0, 1, 0), None, None, "d3q27", "mrt", True),
+             ("f32", (1, 1, 1), sol, lid, "d3q27", "mrt", True),
+             ("f64", (0, 1, 0), None, None, "d3q27", "mrt", False)]
     for storage, walls, solid, wv, lattice, coll, fused in cases:
         lat = Lattice(dims, walls, storage, RATES, solid=solid, wall_velocity=wv, lattice=lattice, collision=coll)
         assert not lat.uses_fused_pairs  # 8^3 is too small to fill the device: single steps by default
@@ -115,11 +117,11 @@ def test_fused_pairs_by_default_only_on_lattices_that_fill_the_device():
         lat.close()
 
 
-def _run_solid(dims, walls, solid, steps, fused, f0, field, rates=RATES, wall_velocity=None):
+def _run_solid(dims, walls, solid, steps, fused, f0, field, rates=RATES, wall_velocity=None, collision="cascaded"):
     from paper_1801_04586_amd import Lattice
 
     lat = Lattice(dims, walls, "f32", rates, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid,
-                  wall_velocity=wall_velocity)
+                  wall_velocity=wall_velocity, collision=collision)
     lat.set_fused_steps(fused)
     assert lat.uses_fused_pairs == fused
     lat.set_populations(torch.from_numpy(f0))
@@ -332,3 +334,21 @@ def test_trajectory_refuses_shared_buffers():
     lat.ctx.trajectory(lat.state, [s1, s2])
     torch.cuda.synchronize()
     lat.close()
+
+
+@pytest.mark.parametrize("dims,walls,frac,moving", [((67, 19, 13), (0, 0, 0), 0.0, False),
+                                                    ((33, 9, 40), (1, 1, 1), 0.2, False),
+                                                    ((40, 12, 3), (0, 1, 1), 0.0, False),
+                                                    ((35, 13, 11), (1, 1, 1), 0.15, True),
+                                                    ((38, 14, 9), (0, 1, 0), 0.0, True)])
+def test_fused_mrt_pairs_are_bitwise_single_steps(dims, walls, frac, moving):
+    """The raw-moment MRT of Appendix B in fused pairs: periodic with a force field, walls, solids and
+    moving faces, against single MRT steps."""
+    g, f0 = _start_walls(dims, walls, 81)
+    field = workloads.gaussian_force(dims, 1e-4, 82)
+    solid = workloads.random_solids(dims, frac, 83) if frac else None
+    wv = _moving_faces(walls, 84) if moving else None
+    for steps in (2, 5):
+        a, _ = _run_solid(dims, walls, solid, steps, True, f0, field, RATES, wv, "mrt")
+        b, _ = _run_solid(dims, walls, solid, steps, False, f0, field, RATES, wv, "mrt")
+        assert torch.equal(a, b), (dims, walls, frac, moving, steps)
