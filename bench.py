@@ -248,7 +248,11 @@ def v_kolmogorov_d3q19(storage):
     def run(b: Bench):
         lat = b.kolmogorov_lattice(storage, lattice="d3q19")
         lat.step(3)
-        r = b.record(b.nodes, b.step_ms(lat), bytes_per_node(storage, True, False, q=19), launch="one step")
+        bpn = bytes_per_node(storage, True, False, q=19)
+        r = b.record(b.nodes, b.step_ms(lat), bpn, launch="two fused steps" if lat.uses_fused_pairs else "one step")
+        if lat.uses_fused_pairs:
+            lat.set_fused_steps(False)
+            r["single_step"] = b.record(b.nodes, b.step_ms(lat), bpn)
         b.done(lat)
         return r
     return run

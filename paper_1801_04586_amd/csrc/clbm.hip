@@ -54,7 +54,7 @@ struct clbm_ctx {
     int num_cu;        // compute units of the device
     int device;        // device the context was created on
     double *scratch;   // that device's address of the static scratch (clbm_adjoint_step_noalloc)
-    int t2_slots[2][2][3];  // resident blocks of the fused kernel, by (links, force field, collision); 0 = unknown
+    int t2_slots[2][2][3][2];  // resident blocks of the fused kernel, by (links, force field, collision, D3Q19); 0 = unknown
     char err[clbm_host::kErrLen];
 };
 
@@ -230,16 +230,15 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
     });
 }
 
-// Two fused steps per launch apply to D3Q27 lattices with FP32 storage and the
-// cascaded collision, either periodic or with a link table (solid nodes or walls,
-// moving or not).  FP64 does not fit the LDS groups at
-// this tile size; for 16-bit storage (half the bytes of FP32) the single-step
-// kernel is faster, the fused kernel's cost per step being set by its arithmetic
-// and barriers rather than by memory; and the MRT's larger register footprint
-// leaves the fused kernel two blocks per CU, slower than single steps.
+// Two fused steps per launch apply to lattices with FP32 storage (D3Q27 with the
+// cascaded collision or the MRT, D3Q19 with the cascaded collision), either
+// periodic or with a link table (solid nodes or walls, moving or not).  FP64 does
+// not fit the LDS groups at this tile size; for 16-bit storage (half the bytes of
+// FP32) the single-step kernel is faster, the fused kernel's cost per step being
+// set by its arithmetic and barriers rather than by memory.
 bool fused_kind(const clbm_desc &d)
 {
-    return d.lattice == CLBM_D3Q27 && d.storage == CLBM_F32;
+    return d.storage == CLBM_F32;
 }
 
 // A lattice too small to give the fused kernel two blocks per compute unit (tile
@@ -270,13 +269,14 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         using R = typename Traits<S>::R;
         constexpr bool FIELD = decltype(field_tag)::value;
         constexpr bool SOLID = decltype(solid_tag)::value;
-        auto launch = [&](auto cc) {
+        auto launch = [&](auto cc, auto qq) {
             constexpr int C = decltype(cc)::value;
+            constexpr int Q = decltype(qq)::value;
             constexpr unsigned dyn_lds = SOLID ? 0u : kT2PadLds;
-            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C];
+            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C][Q == 19 ? 1 : 0];
             if (slots == 0) {
                 int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID>, kT2Block,
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID, Q>, kT2Block,
                                                                  dyn_lds) != hipSuccess ||
                     per_cu < 1)
                     per_cu = 1;
@@ -286,14 +286,18 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
             tg.zchunk = (c->geom.nz + nchunks_req - 1) / nchunks_req;
             const uint32_t nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
             const unsigned blocks = tiles * nchunks;
-            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID>), dim3(blocks), dim3(kT2Block), dyn_lds, c->stream,
+            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID, Q>), dim3(blocks), dim3(kT2Block), dyn_lds, c->stream,
                                static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg, c->links,
                                static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
             return check_launch(c, "fused two-step kernel launch");
         };
-        if (coll == kCascadedHigh1) return launch(std::integral_constant<int, kCascadedHigh1>{});
-        if (coll == kMrt) return launch(std::integral_constant<int, kMrt>{});
-        return launch(std::integral_constant<int, kCascaded>{});
+        using Q27 = std::integral_constant<int, 27>;
+        // D3Q19 (Appendix A) takes the general cascaded collision only
+        if (c->d.lattice == CLBM_D3Q19)
+            return launch(std::integral_constant<int, kCascaded>{}, std::integral_constant<int, 19>{});
+        if (coll == kCascadedHigh1) return launch(std::integral_constant<int, kCascadedHigh1>{}, Q27{});
+        if (coll == kMrt) return launch(std::integral_constant<int, kMrt>{}, Q27{});
+        return launch(std::integral_constant<int, kCascaded>{}, Q27{});
     };
     if (c->links)
         return c->d.force != nullptr ? go(float{}, std::true_type{}, std::true_type{})

@@ -609,7 +609,7 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
 }
 
 // (the waves-per-EU bound keeps the register budget at or below 128)
-template <typename S, bool FIELD, int COLL, bool SOLID>
+template <typename S, bool FIELD, int COLL, bool SOLID, int Q = 27>
 __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) void k_step2(
     const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const uint32_t *__restrict__ links,
     const typename Traits<S>::R *__restrict__ field, Forcing<typename Traits<S>::R> fo,
@@ -702,15 +702,19 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             lm_b = lm;
             if (lm == 0u) {
                 sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });  // solid: the rest state, as step_node
-            } else if (__all(lm == all_links<27>())) {
+            } else if (__all(lm == all_links<Q>())) {
                 const S *__restrict__ pl = src;  // plane i, planes in increasing order
                 uint64_t po = 0;
                 sfor<0, 27>([&](auto II) {
                     constexpr int i = decltype(II)::value, t = slot_of_pop(i);
-                    uint32_t off;
-                    link_open<t, false, false>(nb, 0u, off);
-                    v[t] = to_real(load_at(pl, off * es));
-                    if constexpr (i < 26) pl = next_plane(src, po, plane_bytes);
+                    if constexpr (i < Q) {  // D3Q19: populations 0-18 (the corners come last in Eq. (1))
+                        uint32_t off;
+                        link_open<t, false, false>(nb, 0u, off);
+                        v[t] = to_real(load_at(pl, off * es));
+                        if constexpr (i < Q - 1) pl = next_plane(src, po, plane_bytes);
+                    } else {
+                        v[t] = R(0);
+                    }
                 });
             } else {
                 // the gather of Eq. (8) with its checks, planes in increasing order: a blocked
@@ -721,7 +725,9 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
                 uint64_t po = 0;
                 sfor<0, 27>([&](auto II) {
                     constexpr int i = decltype(II)::value, t = slot_of_pop(i);
-                    if constexpr (t == 13) {
+                    if constexpr (i >= Q) {
+                        v[t] = R(0);
+                    } else if constexpr (t == 13) {
                         v[t] = to_real(load_at(pl, n * es));
                     } else {
                         constexpr int ib = pop_of_slot(26 - t);
@@ -733,9 +739,9 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
                             reinterpret_cast<const S *>(reinterpret_cast<const char *>(src) + pb * ib);
                         const S val = ok ? load_at(pl, off * es) : load_at(own, n * es);
                         v[t] = to_real(val);
-                        if (mf && !ok) v[t] += wall_term<t, 27, R>(nb, g);
+                        if (mf && !ok) v[t] += wall_term<t, Q, R>(nb, g);
                     }
-                    if constexpr (i < 26) pl = next_plane(src, po, plane_bytes);
+                    if constexpr (i < Q - 1) pl = next_plane(src, po, plane_bytes);
                 });
             }
         } else {
@@ -743,16 +749,20 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             uint64_t po = 0;
             sfor<0, 27>([&](auto II) {
                 constexpr int i = decltype(II)::value, t = slot_of_pop(i);
-                uint32_t off;
-                link_open<t, false, false>(nb, 0u, off);
-                v[t] = to_real(load_at(pl, off * es));
-                if constexpr (i < 26) pl = next_plane(src, po, plane_bytes);
+                if constexpr (i < Q) {
+                    uint32_t off;
+                    link_open<t, false, false>(nb, 0u, off);
+                    v[t] = to_real(load_at(pl, off * es));
+                    if constexpr (i < Q - 1) pl = next_plane(src, po, plane_bytes);
+                } else {
+                    v[t] = R(0);
+                }
             });
         }
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
         __builtin_amdgcn_s_setprio(0);
-        node_update<COLL>(v, Fx, Fy, Fz, rt);
+        node_update<COLL, Q>(v, Fx, Fy, Fz, rt);
         const int r0 = zm(p);
         sfor<0, 9>([&](auto J) {
             constexpr int j = decltype(J)::value;  // j = 3 a + b; slot 3 j + c with c = e_z + 1
@@ -791,12 +801,20 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             constexpr int a = sa(t), bb = sb(t), c = sc(t), j = 3 * a + bb;
             return ((c == 0 ? rz : c) * 9 + j) * kT2H + hn + (1 - bb) * kT2HX + (1 - a);
         };
+        // the pulled value of slot t (D3Q19: the corner slots hold no population and stay 0)
+        auto pull = [&](auto TT) -> float {
+            constexpr int t = decltype(TT)::value;
+            if constexpr (has_slot<Q>(t))
+                return rf[pulled_at(TT)];
+            else
+                return 0.0f;
+        };
         if constexpr (SOLID) {
             const uint32_t lm = lm_a;
             if (lm == 0u) {
                 sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });
-            } else if (__all(lm == all_links<27>())) {
-                sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = rf[pulled_at(TT)]; });
+            } else if (__all(lm == all_links<Q>())) {
+                sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = pull(TT); });
             } else {
                 // a blocked link returns the node's own opposite population of step t+1 (Eq. (8)),
                 // plus the momentum of a moving wall as in gather()
@@ -810,8 +828,8 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
                 sfor<0, 27>([&](auto TT) {
                     constexpr int t = decltype(TT)::value;
                     constexpr int jo = 8 - (3 * sa(t) + sb(t)), co = 2 - sc(t);
-                    const float nbv = rf[pulled_at(TT)];
-                    if constexpr (t == 13) {
+                    const float nbv = pull(TT);
+                    if constexpr (t == 13 || !has_slot<Q>(t)) {
                         v[t] = nbv;
                     } else {
                         float own;
@@ -821,12 +839,12 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
                             own = rf[((co == 0 ? ro : 1) * 9 + jo) * kT2H + hn];
                         const bool open = (lm >> t) & 1u;
                         v[t] = open ? nbv : own;
-                        if (mf && !open) v[t] += wall_term<t, 27, R>(nb, g);
+                        if (mf && !open) v[t] += wall_term<t, Q, R>(nb, g);
                     }
                 });
             }
         } else {
-            sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = rf[pulled_at(TT)]; });
+            sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = pull(TT); });
         }
         R Fx, Fy, Fz;
         if constexpr (kFieldAhead) {
@@ -835,22 +853,23 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         } else {
             force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
         }
-        node_update<COLL>(v, Fx, Fy, Fz, rt);
+        node_update<COLL, Q>(v, Fx, Fy, Fz, rt);
         const uint32_t nb_off = n * static_cast<uint32_t>(sizeof(S));
         if constexpr (SOLID) {
             // the link-table variant holds too many uniform values to keep the 27 destination
             // plane addresses as well: stores in plane order with the running offset
             S *__restrict__ pl = dst;
             uint64_t po = 0;
-            sfor<0, 27>([&](auto II) {
+            sfor<0, Q>([&](auto II) {
                 constexpr int i = decltype(II)::value, t = slot_of_pop(i);
                 store_at(pl, nb_off, to_store<S>(v[t]));
-                if constexpr (i < 26) pl = next_plane(dst, po, plane_bytes);
+                if constexpr (i < Q - 1) pl = next_plane(dst, po, plane_bytes);
             });
         } else {
             sfor<0, 27>([&](auto TT) {
                 constexpr int t = decltype(TT)::value;
-                store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.P, nb_off, to_store<S>(v[t]));
+                if constexpr (has_slot<Q>(t))
+                    store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.P, nb_off, to_store<S>(v[t]));
             });
         }
     };

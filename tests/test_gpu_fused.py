@@ -1,5 +1,6 @@
 """Fused two-step launches (clbm_run on FP32 D3Q27 lattices with the cascaded or the
-MRT collision: periodic, walled, moving walls, solid nodes) are bitwise identical to single steps,
+MRT collision, and on FP32 D3Q19 lattices: periodic, walled, moving walls, solid nodes) are bitwise
+identical to single steps,
 across ragged tiles, thin lattices, odd step counts, both collision paths, with
 or without a force field, every wall combination, random solids and packed
 spheres; and they match the oracle."""
@@ -75,7 +76,9 @@ def test_fused_pairs_apply_to_fp32_cascaded_d3q27_lattices():
              ("f64", (0, 1, 0), sol, None, "d3q27", "cascaded", False),
              ("f32", (0, 1, 0), sol, lid, "d3q27", "cascaded", True),
              ("f32", (1, 1, 1), None, lid, "d3q27", "cascaded", True),
-             ("f32", (0, 1, 0), None, None, "d3q19", "cascaded", False),
+             ("f32", (0, 1, 0), None, None, "d3q19", "cascaded", True),
+             ("f32", (1, 1, 1), sol, lid, "d3q19", "cascaded", True),
+             ("f64", (0, 1, 0), None, None, "d3q19", "cascaded", False),
              ("f32", (0, 1, 0), None, None, "d3q27", "mrt", True),
              ("f32", (1, 1, 1), sol, lid, "d3q27", "mrt", True),
              ("f64", (0, 1, 0), None, None, "d3q27", "mrt", False)]
@@ -352,3 +355,53 @@ def test_fused_mrt_pairs_are_bitwise_single_steps(dims, walls, frac, moving):
         a, _ = _run_solid(dims, walls, solid, steps, True, f0, field, RATES, wv, "mrt")
         b, _ = _run_solid(dims, walls, solid, steps, False, f0, field, RATES, wv, "mrt")
         assert torch.equal(a, b), (dims, walls, frac, moving, steps)
+
+
+def _run_q19(dims, walls, solid, steps, fused, f0, field, wall_velocity=None):
+    from paper_1801_04586_amd import Lattice
+
+    lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid,
+                  wall_velocity=wall_velocity, lattice="d3q19")
+    lat.set_fused_steps(fused)
+    assert lat.uses_fused_pairs == fused
+    lat.set_populations(torch.from_numpy(f0))
+    lat.step(steps)
+    out = lat.state.clone()
+    pops = lat.populations().cpu().numpy()
+    lat.close()
+    return out, pops
+
+
+@pytest.mark.parametrize("dims,walls,frac,moving", [((67, 19, 13), (0, 0, 0), 0.0, False),
+                                                    ((16, 8, 3), (0, 0, 0), 0.0, False),
+                                                    ((33, 9, 40), (1, 1, 1), 0.2, False),
+                                                    ((40, 12, 3), (0, 1, 1), 0.0, False),
+                                                    ((5, 7, 2), (1, 0, 1), 0.1, False),
+                                                    ((35, 13, 11), (1, 1, 1), 0.15, True),
+                                                    ((38, 14, 9), (0, 1, 0), 0.0, True)])
+def test_fused_d3q19_pairs_are_bitwise_single_steps(dims, walls, frac, moving):
+    """The D3Q19 scheme of Appendix A in fused pairs (19 planes; the corner slots hold no population),
+    periodic with a force field, with walls, solids and moving faces, against single D3Q19 steps."""
+    g = oracle.Geometry(dims, walls)
+    rho0, u0 = workloads.random_state_fields(dims, 91, du=0.05, drho=0.02)
+    f0 = oracle.init(g, rho0, u0, lattice="d3q19") + workloads.random_populations_perturbation(dims, 92, 1e-3)[:19]
+    field = workloads.gaussian_force(dims, 1e-4, 93)
+    solid = workloads.random_solids(dims, frac, 94) if frac else None
+    wv = _moving_faces(walls, 95) if moving else None
+    for steps in (2, 5):
+        a, _ = _run_q19(dims, walls, solid, steps, True, f0, field, wv)
+        b, _ = _run_q19(dims, walls, solid, steps, False, f0, field, wv)
+        assert torch.equal(a, b), (dims, walls, frac, moving, steps)
+
+
+def test_fused_d3q19_pairs_match_the_oracle():
+    dims, walls = (37, 15, 10), (0, 1, 1)
+    g = oracle.Geometry(dims, walls)
+    rho0, u0 = workloads.random_state_fields(dims, 96, du=0.05, drho=0.02)
+    f0 = oracle.init(g, rho0, u0, lattice="d3q19") + workloads.random_populations_perturbation(dims, 97, 1e-3)[:19]
+    field = workloads.gaussian_force(dims, 1e-4, 98)
+    solid = workloads.random_solids(dims, 0.1, 99)
+    _, got = _run_q19(dims, walls, solid, 4, True, f0, field)
+    ref = oracle.run(g, f0, RATES, 4, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid, lattice="d3q19")
+    fl = solid == 0
+    assert np.max(np.abs(got[:, fl] - ref[:, fl])) < 5e-8
