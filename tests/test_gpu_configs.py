@@ -26,10 +26,12 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 
-def _lattice(dims, walls, storage, rates, force=(0.0, 0.0, 0.0), field=None, solid=None):
+def _lattice(dims, walls, storage, rates, force=(0.0, 0.0, 0.0), field=None, solid=None, lattice="d3q27",
+             collision="cascaded"):
     from paper_1801_04586_amd import Lattice
 
-    return Lattice(dims, walls, storage, rates, force=force, force_field=field, solid=solid)
+    return Lattice(dims, walls, storage, rates, force=force, force_field=field, solid=solid, lattice=lattice,
+                   collision=collision)
 
 
 def _window(dims, walls, c, k):
@@ -49,7 +51,8 @@ def _window(dims, walls, c, k):
     return tuple(o), tuple(w), idx
 
 
-def _cone_parity(lat, dims, walls, rates, k, samples, rho0=None, u0=None, force=(0, 0, 0), field=None, solid=None):
+def _cone_parity(lat, dims, walls, rates, k, samples, rho0=None, u0=None, force=(0, 0, 0), field=None, solid=None,
+                 lattice="d3q27", model="cascaded"):
     """Max |f_gpu - f_oracle| over the sampled nodes after k steps from f_eq(rho0, u0)."""
     got = lat.sample(samples)
     err = 0.0
@@ -58,8 +61,9 @@ def _cone_parity(lat, dims, walls, rates, k, samples, rho0=None, u0=None, force=
         sub = lambda a: None if a is None else np.ascontiguousarray(a[..., iz[:, None, None], iy[None, :, None],
                                                                          ix[None, None, :]])
         g = oracle.Geometry(dims, walls, o, w)
-        f = oracle.init(g, sub(rho0), sub(u0))
-        f = oracle.run(g, f, rates, k, force=force, force_field=sub(field), solid=sub(solid))
+        f = oracle.init(g, sub(rho0), sub(u0), lattice=lattice, model=model)
+        f = oracle.run(g, f, rates, k, force=force, force_field=sub(field), solid=sub(solid), lattice=lattice,
+                       model=model)
         ref = f[:, c[2] - o[2], c[1] - o[1], c[0] - o[0]]  # the node sits at offset c - origin
         if solid is not None and solid[c[2], c[1], c[0]]:
             continue
@@ -198,6 +202,29 @@ def test_kolmogorov_512_sampled_parity_fp32(kolmogorov_inputs):
     err = _cone_parity(lat, cfg.dims, cfg.walls, cfg.rates(), k, samples, None, u0, field=F32)
     assert err < 5e-9, err
     lat.close()
+
+
+@pytest.mark.parametrize("lattice,collision", [("d3q19", "cascaded"), ("d3q27", "mrt")])
+def test_kolmogorov_512_sampled_parity_fused_d3q19_and_mrt(lattice, collision, kolmogorov_inputs):
+    """The fused pairs of the D3Q19 scheme (Appendix A) and of the MRT (Appendix B) at the benchmark's
+    512^3 size and launch configuration (one fused pair and one single step), against the oracle on the
+    light cones of sampled nodes, at the bound of the D3Q27 FP32 fused case."""
+    cfg = workloads.KOLMOGOROV512
+    u0, F = kolmogorov_inputs
+    k = 3
+    lat = _lattice(cfg.dims, cfg.walls, "f32", cfg.rates(), field=F, lattice=lattice, collision=collision)
+    assert lat.uses_fused_pairs
+    lat.init(None, u0)
+    lat.step(k)
+    samples = _samples(cfg.dims, 10, 17, include=[(0, 0, 0), (511, 511, 511), (255, 300, 0)])
+    F32 = lat.force_field.double().cpu().numpy()
+    err = _cone_parity(lat, cfg.dims, cfg.walls, cfg.rates(), k, samples, None, u0, field=F32, lattice=lattice,
+                       model=collision)
+    print(f"Kolmogorov 512^3 {lattice} {collision}, fused pair + one step: max |f - f_oracle| {err:.2e}")
+    assert err < 5e-9, err
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", 5e-15), ("f16", 1e-6), ("bf16", 5e-6)])
