@@ -533,8 +533,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 }
 
 // ------------------------------------------------------------------ two fused steps (temporal blocking)
-// Two time steps per launch on FP32 D3Q27 lattices (cascaded collision).  A block
-// owns a 32 x 12 tile of (x, y) columns and marches along a chunk of z planes.
+// Two time steps per launch on FP32 lattices: D3Q27 with the cascaded collision
+// or the MRT of Appendix B, and D3Q19 (Q = 19: only the 19 population planes are
+// read and written, the corner slots hold 0).  A block owns a 32 x 12 tile of
+// (x, y) columns and marches along a chunk of z planes.
 // For each plane it first runs step t -> t+1 on the tile plus a one-node halo
 // (34 x 14 nodes, pulling from HBM), keeping the results in LDS, and then step
 // t+1 -> t+2 on the tile plane below, pulling those results from LDS and
@@ -556,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 // links) the bounce-back of Eq. (8) in step t+2 takes the node's own opposite
 // population from step t+1 (plus the momentum of a moving wall).  Each tile
 // node is then stepped in t+2 by the thread that stepped it in t+1 (threads 0
-// to 383 take the tile, 384 to 475 the halo ring), whose registers hold the
+// to 383 take the tile, wavefronts 6 and 7 the halo ring), whose registers hold the
 // node's e_z = +1 group and link word; the e_z = 0 group of plane z is in LDS,
 // and the e_z = -1 groups alternate between two LDS slots by plane parity so
 // that plane z's stays readable while plane z+1's is written (68.5 KB per block).
@@ -567,6 +569,13 @@ __host__ __device__ constexpr int slot_of_pop(int i)
         if (pop_of_slot(t) == i) return t;
     return -1;
 }
+constexpr bool slot_of_pop_inverts()
+{
+    for (int t = 0; t < 27; ++t)
+        if (slot_of_pop(pop_of_slot(t)) != t) return false;
+    return true;
+}
+static_assert(slot_of_pop_inverts(), "pop_of_slot is a bijection of the 27 slots and slot_of_pop its inverse");
 
 // Address of population plane i + 1 from that of plane i, for loops over the planes in
 // increasing order inside the fused kernel's plane loop.  Left to itself the compiler
