@@ -54,7 +54,7 @@ struct clbm_ctx {
     int num_cu;        // compute units of the device
     int device;        // device the context was created on
     double *scratch;   // that device's address of the static scratch (clbm_adjoint_step_noalloc)
-    int t2_slots[2][2][3][2];  // resident blocks of the fused kernel, by (links, force field, collision, D3Q19); 0 = unknown
+    int t2_slots[2][2][2][3][2];  // resident blocks of the fused kernel, by (FP64, links, force field, collision, D3Q19); 0 = unknown
     char err[clbm_host::kErrLen];
 };
 
@@ -232,13 +232,16 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
 
 // Two fused steps per launch apply to lattices with FP32 storage (D3Q27 with the
 // cascaded collision or the MRT, D3Q19 with the cascaded collision), either
-// periodic or with a link table (solid nodes or walls, moving or not).  FP64 does
-// not fit the LDS groups at this tile size; for 16-bit storage (half the bytes of
-// FP32) the single-step kernel is faster, the fused kernel's cost per step being
-// set by its arithmetic and barriers rather than by memory.
+// periodic or with a link table (solid nodes or walls, moving or not), and to
+// periodic lattices with FP64 storage (the same schemes; one block per compute
+// unit, whose LDS groups of doubles fill 103 KB, and no link-table variant).  For
+// 16-bit storage (half the bytes of FP32) the single-step kernel is faster, the
+// fused kernel's cost per step being set by its arithmetic and barriers rather
+// than by memory.
 bool fused_kind(const clbm_desc &d)
 {
-    return d.storage == CLBM_F32;
+    const bool walls = d.wall[0] || d.wall[1] || d.wall[2];
+    return d.storage == CLBM_F32 || (d.storage == CLBM_F64 && !d.solid && !walls);
 }
 
 // A lattice too small to give the fused kernel two blocks per compute unit (tile
@@ -273,7 +276,7 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
             constexpr int C = decltype(cc)::value;
             constexpr int Q = decltype(qq)::value;
             constexpr unsigned dyn_lds = SOLID ? 0u : kT2PadLds;
-            int &slots = c->t2_slots[SOLID ? 1 : 0][FIELD ? 1 : 0][C][Q == 19 ? 1 : 0];
+            int &slots = c->t2_slots[sizeof(S) == 8 ? 1 : 0][SOLID ? 1 : 0][FIELD ? 1 : 0][C][Q == 19 ? 1 : 0];
             if (slots == 0) {
                 int per_cu = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID, Q>, kT2Block,
@@ -299,6 +302,11 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         if (coll == kMrt) return launch(std::integral_constant<int, kMrt>{}, Q27{});
         return launch(std::integral_constant<int, kCascaded>{}, Q27{});
     };
+    if (c->d.storage == CLBM_F64) {  // periodic lattices only (fused_kind)
+        if (c->links) return fail(c, CLBM_EINVAL, "fused FP64 pairs take no link table");
+        return c->d.force != nullptr ? go(double{}, std::true_type{}, std::false_type{})
+                                     : go(double{}, std::false_type{}, std::false_type{});
+    }
     if (c->links)
         return c->d.force != nullptr ? go(float{}, std::true_type{}, std::true_type{})
                                      : go(float{}, std::false_type{}, std::true_type{});

@@ -533,10 +533,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 }
 
 // ------------------------------------------------------------------ two fused steps (temporal blocking)
-// Two time steps per launch on FP32 lattices: D3Q27 with the cascaded collision
-// or the MRT of Appendix B, and D3Q19 (Q = 19: only the 19 population planes are
-// read and written, the corner slots hold 0).  A block owns a 32 x 12 tile of
-// (x, y) columns and marches along a chunk of z planes.
+// Two time steps per launch on FP32 lattices (and periodic FP64 lattices): D3Q27
+// with the cascaded collision or the MRT of Appendix B, and D3Q19 (Q = 19: only the
+// 19 population planes are read and written, the corner slots hold 0).  A block
+// owns a 32 x 12 tile of (x, y) columns and marches along a chunk of z planes.
 // For each plane it first runs step t -> t+1 on the tile plus a one-node halo
 // (34 x 14 nodes, pulling from HBM), keeping the results in LDS, and then step
 // t+1 -> t+2 on the tile plane below, pulling those results from LDS and
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 // thread keeps its halo node's e_z = 0 group for one plane iteration and its
 // e_z = +1 group for two in registers and writes a group to LDS only in the
 // iteration that pulls it, so LDS holds just three groups of 9 x 476 values
-// (51 KB per block).  The tile height was chosen by measurement (heights 6 to 16
+// (51 KB per block in FP32; FP64 doubles it to 103 KB, one block per CU).  The tile height was chosen by measurement (heights 6 to 16
 // on 512^3, 640x320x320 and 128^3 lattices; 12 was fastest on all three).
 //
 // With solid nodes or walls (SOLID: the link table holds every node's open
@@ -598,6 +598,23 @@ __device__ __forceinline__ T *next_plane(T *base, uint64_t &off, uint64_t stride
     return reinterpret_cast<T *>(reinterpret_cast<B *>(base) + off);
 }
 
+// The value a stored state holds in slot t for the post-collision deviation d: storage types that
+// hold deviations round d, FP64 storage holds f = d + w_t (as step_node stores it).
+template <typename S, int Q, int t, typename R>
+__device__ __forceinline__ R stored_value(R d)
+{
+    if constexpr (!Traits<S>::kDev) d += lattice_weight<Q, R>(t);
+    return static_cast<R>(to_store<S>(d));
+}
+
+// The deviation d = f - w_t the node update takes, from a value as a state holds it.
+template <typename S, typename R, int Q>
+__device__ __forceinline__ void to_deviations(R (&v)[27])
+{
+    if constexpr (!Traits<S>::kDev)
+        sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= lattice_weight<Q, R>(decltype(T)::value); });
+}
+
 constexpr int kT2X = 32, kT2Y = 12;
 constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 476 nodes
 constexpr int kT2Block = (kT2H + 63) / 64 * 64;                             // 512 threads, eight wavefronts
@@ -617,18 +634,20 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
     return static_cast<uint32_t>(r < 0 ? r + static_cast<int>(n) : r);
 }
 
-// (the waves-per-EU bound keeps the register budget at or below 128)
+// (the waves-per-EU bound keeps the register budget at or below 128 for FP32 arithmetic; FP64
+// arithmetic, whose values take two registers each, gets 256 and one block per CU)
 template <typename S, bool FIELD, int COLL, bool SOLID, int Q = 27>
-__global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) void k_step2(
+__global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(sizeof(typename Traits<S>::R) == 8 ? 2 : 4))) void k_step2(
     const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const uint32_t *__restrict__ links,
     const typename Traits<S>::R *__restrict__ field, Forcing<typename Traits<S>::R> fo,
     Rates<typename Traits<S>::R> rt)
 {
     using R = typename Traits<S>::R;
-    static_assert(std::is_same<R, float>::value, "the LDS ring holds FP32 values");
+    static_assert(!SOLID || std::is_same<R, float>::value, "the link-table variant is built for FP32 only");
     // [0]: e_z = -1 group of plane z+1, [1]: e_z = 0 group of plane z, [2]: e_z = +1 group of plane z-1;
-    // with SOLID, [0] and [3] hold the e_z = -1 groups of even and odd planes
-    __shared__ float ring[SOLID ? 4 : 3][9][kT2H];
+    // with SOLID, [0] and [3] hold the e_z = -1 groups of even and odd planes.  The ring holds the
+    // arithmetic type, which represents every storable value exactly.
+    __shared__ R ring[SOLID ? 4 : 3][9][kT2H];
     auto zm = [](int p) { return SOLID && (p & 1) ? 3 : 0; };
 
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
@@ -683,7 +702,7 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
     const uint64_t plane_bytes = static_cast<uint64_t>(g.P) * sizeof(S);
     // groups of the halo node's intermediate values kept in registers until the plane that pulls
     // them: e_z = 0 of plane p, e_z = +1 of planes p - 1 and p (p: the last plane computed)
-    float keep0[9], keep2a[9], keep2b[9];
+    R keep0[9], keep2a[9], keep2b[9];
     uint32_t lm_a = 0, lm_b = 0;  // SOLID: the halo node's link words in planes p - 1 and p
     // SOLID: the link word of the next plane, loaded one plane ahead.  The checked pulls need it
     // for their addresses, so loading it with them would put a second HBM round trip on the path
@@ -767,6 +786,7 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
                     v[t] = R(0);
                 }
             });
+            to_deviations<S, R, Q>(v);
         }
         R Fx, Fy, Fz;
         force_at<FIELD>(fo, field, g.N, n, Fx, Fy, Fz);
@@ -775,10 +795,10 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         const int r0 = zm(p);
         sfor<0, 9>([&](auto J) {
             constexpr int j = decltype(J)::value;  // j = 3 a + b; slot 3 j + c with c = e_z + 1
-            ring[r0][j][hs] = static_cast<float>(to_store<S>(v[3 * j + 0]));  // the value a stored state would hold
+            ring[r0][j][hs] = stored_value<S, Q, 3 * j + 0>(v[3 * j + 0]);  // the value a stored state would hold
             keep2a[j] = keep2b[j];
-            keep0[j] = static_cast<float>(to_store<S>(v[3 * j + 1]));
-            keep2b[j] = static_cast<float>(to_store<S>(v[3 * j + 2]));
+            keep0[j] = stored_value<S, Q, 3 * j + 1>(v[3 * j + 1]);
+            keep2b[j] = stored_value<S, Q, 3 * j + 2>(v[3 * j + 2]);
         });
     };
 
@@ -803,7 +823,7 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         const int hn = SOLID ? hs : (cy + 1) * kT2HX + (cx + 1);  // LDS index of the tile node
         R v[27];
         // slot t pulls from the halo position of x - e; index into the ring viewed as one array
-        const float *rf = &ring[0][0][0];
+        const R *rf = &ring[0][0][0];
         const int rz = zm(z + 1);
         auto pulled_at = [&](auto TT) -> int {
             constexpr int t = decltype(TT)::value;
@@ -811,12 +831,12 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             return ((c == 0 ? rz : c) * 9 + j) * kT2H + hn + (1 - bb) * kT2HX + (1 - a);
         };
         // the pulled value of slot t (D3Q19: the corner slots hold no population and stay 0)
-        auto pull = [&](auto TT) -> float {
+        auto pull = [&](auto TT) -> R {
             constexpr int t = decltype(TT)::value;
             if constexpr (has_slot<Q>(t))
                 return rf[pulled_at(TT)];
             else
-                return 0.0f;
+                return R(0);
         };
         if constexpr (SOLID) {
             const uint32_t lm = lm_a;
@@ -837,11 +857,11 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
                 sfor<0, 27>([&](auto TT) {
                     constexpr int t = decltype(TT)::value;
                     constexpr int jo = 8 - (3 * sa(t) + sb(t)), co = 2 - sc(t);
-                    const float nbv = pull(TT);
+                    const R nbv = pull(TT);
                     if constexpr (t == 13 || !has_slot<Q>(t)) {
                         v[t] = nbv;
                     } else {
-                        float own;
+                        R own;
                         if constexpr (co == 2)
                             own = keep2a[jo];
                         else
@@ -854,6 +874,7 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
             }
         } else {
             sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = pull(TT); });
+            to_deviations<S, R, Q>(v);
         }
         R Fx, Fy, Fz;
         if constexpr (kFieldAhead) {
@@ -877,13 +898,16 @@ __global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(4))) v
         } else {
             sfor<0, 27>([&](auto TT) {
                 constexpr int t = decltype(TT)::value;
-                if constexpr (has_slot<Q>(t))
-                    store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.P, nb_off, to_store<S>(v[t]));
+                if constexpr (has_slot<Q>(t)) {
+                    R val = v[t];
+                    if constexpr (!Traits<S>::kDev) val += lattice_weight<Q, R>(t);
+                    store_at(dst + static_cast<size_t>(pop_of_slot(t)) * g.P, nb_off, to_store<S>(val));
+                }
             });
         }
     };
 
-    sfor<0, 9>([&](auto J) { keep2b[decltype(J)::value] = 0.0f; });
+    sfor<0, 9>([&](auto J) { keep2b[decltype(J)::value] = R(0); });
     first_step(z0 - 1);  // keep2b <- e_z = +1 group of plane z0 - 1
     first_step(z0);      // keep0 <- e_z = 0 of z0, keep2a <- +1 of z0 - 1, keep2b <- +1 of z0
     for (int z = z0; z < z1; ++z) {

@@ -227,23 +227,27 @@ def test_kolmogorov_512_sampled_parity_fused_d3q19_and_mrt(lattice, collision, k
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 5e-15), ("f16", 1e-6), ("bf16", 5e-6)])
-def test_kolmogorov_512_sampled_parity_single_step_storages(storage, tol, kolmogorov_inputs):
-    """The single-step kernels the benchmark times for FP64, FP16 and BF16 storage at 512^3 (two steps)
-    against the oracle on the light cones of sampled nodes.  The oracle starts from the exact
-    equilibrium, the GPU from its storage-rounded deviations, so the bound is a few roundings of
-    deviations of order 1e-3 in the storage type (measured 5e-16, 1.1e-7 and 7e-7)."""
+@pytest.mark.parametrize("storage,tol,fused", [("f64", 5e-15, True), ("f64", 5e-15, False), ("f16", 1e-6, False),
+                                               ("bf16", 5e-6, False)])
+def test_kolmogorov_512_sampled_parity_fp64_and_16_bit_storages(storage, tol, fused, kolmogorov_inputs):
+    """The kernels the benchmark times at 512^3 for FP64 storage (fused pairs: one pair and one single
+    step; single steps are checked too) and for FP16 and BF16 storage (two single steps), against the
+    oracle on the light cones of sampled nodes.  The oracle starts from the exact equilibrium, the GPU
+    from its storage-rounded deviations, so the bound is a few roundings of deviations of order 1e-3
+    in the storage type (measured 5e-16, 1.1e-7 and 7e-7)."""
     cfg = workloads.KOLMOGOROV512
     u0, F = kolmogorov_inputs
-    k = 2
+    k = 3 if fused else 2
     lat = _lattice(cfg.dims, cfg.walls, storage, cfg.rates(), field=F)
-    assert not lat.uses_fused_pairs
+    assert lat.uses_fused_pairs == (storage == "f64")  # the default on this lattice
+    lat.set_fused_steps(fused)
+    assert lat.uses_fused_pairs == fused
     lat.init(None, u0)
     lat.step(k)
     samples = _samples(cfg.dims, 8, 13, include=[(0, 0, 0), (511, 511, 511), (17, 400, 256)])
     Fs = lat.force_field.double().cpu().numpy()
     err = _cone_parity(lat, cfg.dims, cfg.walls, cfg.rates(), k, samples, None, u0, field=Fs)
-    print(f"Kolmogorov 512^3 {storage} storage, {k} single steps: max |f - f_oracle| over the samples {err:.2e}")
+    print(f"Kolmogorov 512^3 {storage} storage, {k} steps, fused {fused}: max |f - f_oracle| over the samples {err:.2e}")
     assert err < tol, err
     lat.close()
     del lat

@@ -1,6 +1,6 @@
 """Fused two-step launches (clbm_run on FP32 D3Q27 lattices with the cascaded or the
-MRT collision, and on FP32 D3Q19 lattices: periodic, walled, moving walls, solid nodes) are bitwise
-identical to single steps,
+MRT collision, and on FP32 D3Q19 lattices: periodic, walled, moving walls, solid nodes; on periodic
+FP64 lattices of both schemes and collisions) are bitwise identical to single steps,
 across ragged tiles, thin lattices, odd step counts, both collision paths, with
 or without a force field, every wall combination, random solids and packed
 spheres; and they match the oracle."""
@@ -40,7 +40,7 @@ def _run(dims, storage, steps, fused, f0, field, rates=RATES):
 
 @pytest.mark.parametrize("dims", [(67, 19, 13), (32, 8, 16), (16, 8, 3), (5, 7, 2), (1, 1, 9), (33, 9, 40),
                                   (96, 17, 1)])
-@pytest.mark.parametrize("storage", ["f32"])
+@pytest.mark.parametrize("storage", ["f32", "f64"])
 @pytest.mark.parametrize("rates", [RATES, RATES_H1], ids=["general", "high1"])
 def test_fused_pairs_are_bitwise_single_steps(dims, storage, rates):
     g, f0 = _start(dims, 3)
@@ -51,23 +51,24 @@ def test_fused_pairs_are_bitwise_single_steps(dims, storage, rates):
         assert torch.equal(a, b), (dims, storage, steps)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64"])
 @pytest.mark.parametrize("rates", [RATES, RATES_H1], ids=["general", "high1"])
-def test_fused_pairs_without_force_field(rates):
+def test_fused_pairs_without_force_field(storage, rates):
     dims = (40, 24, 10)
     g, f0 = _start(dims, 5)
-    a, _ = _run(dims, "f32", 6, True, f0, None, rates)
-    b, _ = _run(dims, "f32", 6, False, f0, None, rates)
+    a, _ = _run(dims, storage, 6, True, f0, None, rates)
+    b, _ = _run(dims, storage, 6, False, f0, None, rates)
     assert torch.equal(a, b)
 
 
-def test_fused_pairs_apply_to_fp32_cascaded_d3q27_lattices():
+def test_fused_pairs_apply_to_fp32_lattices_and_periodic_fp64_lattices():
     from paper_1801_04586_amd import Lattice
 
     dims = (8, 8, 8)
     sol = workloads.random_solids(dims, 0.1, 9)
     lid = {(1, 1): (0.01, 0.0, 0.0)}
     cases = [("f32", (0, 0, 0), None, None, "d3q27", "cascaded", True),
-             ("f64", (0, 0, 0), None, None, "d3q27", "cascaded", False),
+             ("f64", (0, 0, 0), None, None, "d3q27", "cascaded", True),
              ("f16", (0, 0, 0), None, None, "d3q27", "cascaded", False),
              ("bf16", (0, 0, 0), None, None, "d3q27", "cascaded", False),
              ("f32", (0, 1, 0), None, None, "d3q27", "cascaded", True),
@@ -79,9 +80,12 @@ def test_fused_pairs_apply_to_fp32_cascaded_d3q27_lattices():
              ("f32", (0, 1, 0), None, None, "d3q19", "cascaded", True),
              ("f32", (1, 1, 1), sol, lid, "d3q19", "cascaded", True),
              ("f64", (0, 1, 0), None, None, "d3q19", "cascaded", False),
+             ("f64", (0, 0, 0), None, None, "d3q19", "cascaded", True),
+             ("f64", (0, 0, 0), sol, None, "d3q27", "cascaded", False),
              ("f32", (0, 1, 0), None, None, "d3q27", "mrt", True),
              ("f32", (1, 1, 1), sol, lid, "d3q27", "mrt", True),
-             ("f64", (0, 1, 0), None, None, "d3q27", "mrt", False)]
+             ("f64", (0, 1, 0), None, None, "d3q27", "mrt", False),
+             ("f64", (0, 0, 0), None, None, "d3q27", "mrt", True)]
     for storage, walls, solid, wv, lattice, coll, fused in cases:
         lat = Lattice(dims, walls, storage, RATES, solid=solid, wall_velocity=wv, lattice=lattice, collision=coll)
         assert not lat.uses_fused_pairs  # 8^3 is too small to fill the device: single steps by default
@@ -243,13 +247,14 @@ def test_fused_run_with_solids_matches_oracle():
     lat.close()
 
 
-def test_fused_run_matches_oracle():
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-7), ("f64", 1e-14)])
+def test_fused_run_matches_oracle(storage, tol):
     dims = (37, 11, 6)
     g, f0 = _start(dims, 7)
     field = workloads.gaussian_force(dims, 1e-4, 8)
     from paper_1801_04586_amd import Lattice
 
-    lat = Lattice(dims, (0, 0, 0), "f32", RATES, force=(1e-5, -3e-6, 2e-6), force_field=field)
+    lat = Lattice(dims, (0, 0, 0), storage, RATES, force=(1e-5, -3e-6, 2e-6), force_field=field)
     lat.set_fused_steps(True)
     assert lat.uses_fused_pairs
     lat.set_populations(torch.from_numpy(f0))
@@ -257,8 +262,39 @@ def test_fused_run_matches_oracle():
     lat.step(4)
     got = lat.populations().cpu().numpy()
     ref = oracle.run(g, start, RATES, 4, force=(1e-5, -3e-6, 2e-6), force_field=lat.force_field.double().cpu().numpy())
-    assert np.max(np.abs(got - ref)) < 1e-7
+    err = np.max(np.abs(got - ref))
+    print(f"fused {storage} run against the oracle: {err:.2e}")
+    assert err < tol
     lat.close()
+
+
+@pytest.mark.parametrize("lattice,collision", [("d3q19", "cascaded"), ("d3q27", "mrt")])
+def test_fused_fp64_d3q19_and_mrt_pairs_are_bitwise_single_steps_and_match_the_oracle(lattice, collision):
+    """Periodic FP64 lattices of the D3Q19 scheme (Appendix A) and the MRT (Appendix B) in fused pairs,
+    on a ragged lattice with a force field: bitwise the single steps, and within FP64 rounding of the
+    oracle."""
+    from paper_1801_04586_amd import Lattice
+
+    dims = (45, 17, 9)
+    q = 19 if lattice == "d3q19" else 27
+    g = oracle.Geometry(dims)
+    rho0, u0 = workloads.random_state_fields(dims, 111, du=0.05, drho=0.02)
+    f0 = oracle.init(g, rho0, u0, lattice=lattice, model=collision) + \
+        workloads.random_populations_perturbation(dims, 112, 1e-3)[:q]
+    field = workloads.gaussian_force(dims, 1e-4, 113)
+    out = {}
+    for fused in (True, False):
+        lat = Lattice(dims, (0, 0, 0), "f64", RATES, force=(1e-5, -3e-6, 2e-6), force_field=field, lattice=lattice,
+                      collision=collision)
+        lat.set_fused_steps(fused)
+        assert lat.uses_fused_pairs == fused
+        lat.set_populations(torch.from_numpy(f0))
+        lat.step(5)
+        out[fused] = (lat.state.clone(), lat.populations().cpu().numpy())
+        lat.close()
+    assert torch.equal(out[True][0], out[False][0])
+    ref = oracle.run(g, f0, RATES, 5, force=(1e-5, -3e-6, 2e-6), force_field=field, lattice=lattice, model=collision)
+    assert np.max(np.abs(out[True][1] - ref)) < 1e-14
 
 
 @pytest.mark.parametrize("dims,walls,frac", [((67, 19, 13), (0, 0, 0), 0.0), ((45, 26, 9), (1, 1, 1), 0.2)],
@@ -309,7 +345,7 @@ def test_trajectory_keeps_every_state_bitwise(case):
         lat = Lattice(dims, walls, storage, rates, force=(1e-5, 0, 0), force_field=field, solid=solid,
                       wall_velocity=wv)
         lat.set_fused_steps(fused)
-        assert lat.uses_fused_pairs == (fused and storage == "f32")
+        assert lat.uses_fused_pairs == fused
         lat.set_populations(torch.from_numpy(f0))
         src = lat.state.clone()
         for n in (5, 4):

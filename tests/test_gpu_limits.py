@@ -102,7 +102,10 @@ def test_largest_fp32_lattice_2_to_30_nodes_fused_pairs(walls, frac):
     torch.cuda.empty_cache()
 
 
-def test_largest_fp64_lattice_2_to_29_nodes_d3q19():
+@pytest.mark.parametrize("fused", [True, False], ids=["fused_pairs", "single_steps"])
+def test_largest_fp64_lattice_2_to_29_nodes_d3q19(fused):
+    """The largest FP64 lattice (2^29 nodes, D3Q19, periodic): the fused pair it takes by default, and
+    single steps, against the oracle on windows around nodes at the ends of the 32-bit byte offsets."""
     from paper_1801_04586_amd import Lattice
 
     dims = (1024, 1024, 512)
@@ -113,6 +116,9 @@ def test_largest_fp64_lattice_2_to_29_nodes_d3q19():
     field = torch.randn((3, 512, 1024, 1024), device="cuda", generator=gen, dtype=torch.float64)
     field.mul_(1e-4)
     lat = Lattice(dims, (0, 0, 0), "f64", RATES, force_field=field, lattice="d3q19")
+    assert lat.uses_fused_pairs
+    lat.set_fused_steps(fused)
+    assert lat.uses_fused_pairs == fused
     lat.init()
     lat.step(2)
     centres = [(1023, 1023, 511), (1000, 1022, 510), (5, 7, 511)]
