@@ -205,8 +205,9 @@ int clbm_step(clbm_ctx *ctx, const void *src, void *dst);
  * collisions; no walls, no solid nodes), pairs of steps run as one fused
  * launch that keeps the intermediate state on chip (bitwise the same result as
  * two clbm_step calls) when the lattice fills the device: its 32 x 12 (x, y)
- * tile columns times z chunks of 8 planes give at least two blocks per compute
- * unit (CLBM_OPT_* flags override this); otherwise every step is one
+ * tile columns (32 x 16 for FP64 with the cascaded collision) times z chunks of
+ * 8 planes give at least two blocks per compute unit (CLBM_OPT_* flags override
+ * this); otherwise every step is one
  * clbm_step.  nsteps >= 0. */
 int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result);
 

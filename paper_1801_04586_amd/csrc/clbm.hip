@@ -206,6 +206,12 @@ int collision_of(const clbm_ctx *c)
     return c->d.lattice == CLBM_D3Q27 && high_rates_one(c) ? kCascadedHigh1 : kCascaded;
 }
 
+// Rows of the fused kernel's tile on this lattice (D3Q19 takes the general cascaded collision).
+int fused_rows(const clbm_ctx *c)
+{
+    return t2_rows(c->d.storage == CLBM_F64, c->d.lattice == CLBM_D3Q19 ? kCascaded : collision_of(c));
+}
+
 int launch_step(clbm_ctx *c, const void *src, void *dst)
 {
     const int coll = collision_of(c);
@@ -253,7 +259,8 @@ bool fused_pairs(const clbm_ctx *c)
     if ((c->options & CLBM_OPT_SINGLE_STEP) || !fused_kind(c->d)) return false;
     if (!c->links && (c->d.wall[0] || c->d.wall[1] || c->d.wall[2])) return false;
     if (c->options & CLBM_OPT_FUSED_PAIRS) return true;
-    const uint64_t tiles = static_cast<uint64_t>((c->geom.nx + kT2X - 1) / kT2X) * ((c->geom.ny + kT2Y - 1) / kT2Y);
+    const int rows = fused_rows(c);
+    const uint64_t tiles = static_cast<uint64_t>((c->geom.nx + kT2X - 1) / kT2X) * ((c->geom.ny + rows - 1) / rows);
     const uint64_t chunks = c->geom.nz / 8 > 1 ? c->geom.nz / 8 : 1;
     return tiles * chunks >= 2 * static_cast<uint64_t>(c->num_cu);
 }
@@ -262,10 +269,6 @@ using clbm_host::fused_chunks;
 
 int launch_step2(clbm_ctx *c, const void *src, void *dst)
 {
-    T2Geom tg;
-    tg.tiles_x = (c->geom.nx + kT2X - 1) / kT2X;
-    tg.tiles_y = (c->geom.ny + kT2Y - 1) / kT2Y;
-    const uint32_t tiles = tg.tiles_x * tg.tiles_y;
     const int coll = collision_of(c);
     auto go = [&](auto tag, auto field_tag, auto solid_tag) {
         using S = decltype(tag);
@@ -275,11 +278,16 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         auto launch = [&](auto cc, auto qq) {
             constexpr int C = decltype(cc)::value;
             constexpr int Q = decltype(qq)::value;
+            using Tile = T2Tile<R, C>;
+            T2Geom tg;
+            tg.tiles_x = (c->geom.nx + kT2X - 1) / kT2X;
+            tg.tiles_y = (c->geom.ny + Tile::Y - 1) / Tile::Y;
+            const uint32_t tiles = tg.tiles_x * tg.tiles_y;
             constexpr unsigned dyn_lds = SOLID ? 0u : kT2PadLds;
             int &slots = c->t2_slots[sizeof(S) == 8 ? 1 : 0][SOLID ? 1 : 0][FIELD ? 1 : 0][C][Q == 19 ? 1 : 0];
             if (slots == 0) {
                 int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID, Q>, kT2Block,
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2<S, FIELD, C, SOLID, Q>, Tile::Block,
                                                                  dyn_lds) != hipSuccess ||
                     per_cu < 1)
                     per_cu = 1;
@@ -289,7 +297,7 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
             tg.zchunk = (c->geom.nz + nchunks_req - 1) / nchunks_req;
             const uint32_t nchunks = (c->geom.nz + tg.zchunk - 1) / tg.zchunk;
             const unsigned blocks = tiles * nchunks;
-            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID, Q>), dim3(blocks), dim3(kT2Block), dyn_lds, c->stream,
+            hipLaunchKernelGGL((k_step2<S, FIELD, C, SOLID, Q>), dim3(blocks), dim3(Tile::Block), dyn_lds, c->stream,
                                static_cast<const S *>(src), static_cast<S *>(dst), c->geom, tg, c->links,
                                static_cast<const R *>(c->d.force), make_forcing<R>(c->d), make_rates<R>(c->d.s));
             return check_launch(c, "fused two-step kernel launch");

@@ -536,7 +536,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 // Two time steps per launch on FP32 lattices (and periodic FP64 lattices): D3Q27
 // with the cascaded collision or the MRT of Appendix B, and D3Q19 (Q = 19: only the
 // 19 population planes are read and written, the corner slots hold 0).  A block
-// owns a 32 x 12 tile of (x, y) columns and marches along a chunk of z planes.
+// owns a 32 x 12 tile of (x, y) columns (32 x 16 for FP64 with the cascaded
+// collision, see t2_rows) and marches along a chunk of z planes.
 // For each plane it first runs step t -> t+1 on the tile plus a one-node halo
 // (34 x 14 nodes, pulling from HBM), keeping the results in LDS, and then step
 // t+1 -> t+2 on the tile plane below, pulling those results from LDS and
@@ -615,9 +616,22 @@ __device__ __forceinline__ void to_deviations(R (&v)[27])
         sfor<0, 27>([&](auto T) { v[decltype(T)::value] -= lattice_weight<Q, R>(decltype(T)::value); });
 }
 
-constexpr int kT2X = 32, kT2Y = 12;
-constexpr int kT2HX = kT2X + 2, kT2HY = kT2Y + 2, kT2H = kT2HX * kT2HY;  // halo tile, 476 nodes
-constexpr int kT2Block = (kT2H + 63) / 64 * 64;                             // 512 threads, eight wavefronts
+constexpr int kT2X = 32, kT2HX = kT2X + 2;  // tile columns, and with the halo
+// Rows of the tile.  FP32 arithmetic: 12 (two 8-wave blocks per CU; 6 to 16 rows were measured and
+// 12 was fastest).  FP64: the ring of doubles leaves room for one block per CU, and 16 rows (10 waves,
+// 132 KB of LDS, at most 168 registers) ran the cascaded collision 7-16% faster than 12 rows, and 8
+// rows (two 6-wave blocks per CU) 5-15% slower; the MRT, whose FP64 update spills at 168
+// registers, keeps 12 rows and 256 registers (16 rows were 13% slower).
+__host__ __device__ constexpr int t2_rows(bool fp64, int coll) { return fp64 && coll != kMrt ? 16 : 12; }
+template <typename R, int COLL>
+struct T2Tile {
+    static constexpr int Y = t2_rows(sizeof(R) == 8, COLL);
+    static constexpr int HY = Y + 2, H = kT2HX * HY;  // halo tile: 476 nodes at 12 rows, 612 at 16
+    static constexpr int Block = (H + 63) / 64 * 64;  // 512 threads at 12 rows, 640 at 16
+    // waves per SIMD the register budget must allow: 4 (128 registers) for FP32, 2 (256) for the
+    // one 8-wave FP64 block, 3 (168) for the one 10-wave FP64 block
+    static constexpr int WavesPerEU = sizeof(R) == 4 ? 4 : (Block > 512 ? 3 : 2);
+};
 // Dynamic LDS requested with each launch of the variant without a link table: it keeps that
 // kernel at two blocks per CU.  Its 51 KB ring alone would let a third block in whenever
 // the kernel needs 80 VGPRs or fewer, and three blocks per CU ran the 512^3 lattice 27%
@@ -634,16 +648,19 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
     return static_cast<uint32_t>(r < 0 ? r + static_cast<int>(n) : r);
 }
 
-// (the waves-per-EU bound keeps the register budget at or below 128 for FP32 arithmetic; FP64
-// arithmetic, whose values take two registers each, gets 256 and one block per CU)
+// (the waves-per-EU bound sets the register budget: 128 for FP32 arithmetic; FP64 arithmetic,
+// whose values take two registers each, runs one block per CU with 168 or 256)
 template <typename S, bool FIELD, int COLL, bool SOLID, int Q = 27>
-__global__ __launch_bounds__(kT2Block) __attribute__((amdgpu_waves_per_eu(sizeof(typename Traits<S>::R) == 8 ? 2 : 4))) void k_step2(
+__global__ __launch_bounds__((T2Tile<typename Traits<S>::R, COLL>::Block)) __attribute__((
+    amdgpu_waves_per_eu(T2Tile<typename Traits<S>::R, COLL>::WavesPerEU))) void k_step2(
     const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const uint32_t *__restrict__ links,
     const typename Traits<S>::R *__restrict__ field, Forcing<typename Traits<S>::R> fo,
     Rates<typename Traits<S>::R> rt)
 {
     using R = typename Traits<S>::R;
     static_assert(!SOLID || std::is_same<R, float>::value, "the link-table variant is built for FP32 only");
+    static constexpr int kT2Y = T2Tile<R, COLL>::Y, kT2HY = T2Tile<R, COLL>::HY, kT2H = T2Tile<R, COLL>::H;
+    static constexpr int kT2Block = T2Tile<R, COLL>::Block;
     // [0]: e_z = -1 group of plane z+1, [1]: e_z = 0 group of plane z, [2]: e_z = +1 group of plane z-1;
     // with SOLID, [0] and [3] hold the e_z = -1 groups of even and odd planes.  The ring holds the
     // arithmetic type, which represents every storable value exactly.

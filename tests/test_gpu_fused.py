@@ -113,14 +113,22 @@ def test_fused_option_flags():
 
 
 def test_fused_pairs_by_default_only_on_lattices_that_fill_the_device():
-    """Default rule: tile columns (32 x 12) times z chunks of 8 planes must give two blocks per compute unit."""
+    """Default rule: tile columns (32 x 12; 32 x 16 for FP64 with the cascaded collision) times z chunks
+    of 8 planes must give two blocks per compute unit."""
     from paper_1801_04586_amd import Lattice
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    for dims, walls in (((64, 64, 64), (0, 1, 0)), ((128, 128, 128), (0, 0, 0)), ((256, 96, 64), (1, 1, 1))):
-        blocks = -(-dims[0] // 32) * -(-dims[1] // 12) * max(dims[2] // 8, 1)
-        lat = Lattice(dims, walls, "f32", RATES)
-        assert lat.uses_fused_pairs == (blocks >= 2 * cus), (dims, blocks, cus)
+    for dims, walls, storage, coll in (((64, 64, 64), (0, 1, 0), "f32", "cascaded"),
+                                       ((128, 128, 128), (0, 0, 0), "f32", "cascaded"),
+                                       ((256, 96, 64), (1, 1, 1), "f32", "cascaded"),
+                                       ((128, 128, 128), (0, 0, 0), "f64", "cascaded"),
+                                       ((128, 112, 128), (0, 0, 0), "f64", "cascaded"),
+                                       ((128, 112, 128), (0, 0, 0), "f64", "mrt"),
+                                       ((96, 96, 64), (0, 0, 0), "f64", "cascaded")):
+        rows = 16 if storage == "f64" and coll == "cascaded" else 12
+        blocks = -(-dims[0] // 32) * -(-dims[1] // rows) * max(dims[2] // 8, 1)
+        lat = Lattice(dims, walls, storage, RATES, collision=coll)
+        assert lat.uses_fused_pairs == (blocks >= 2 * cus), (dims, storage, coll, blocks, cus)
         lat.close()
 
 
