@@ -18,7 +18,7 @@ those (one lattice per process, for profilers):
   kolmogorov_512_{f64,f16,bf16}                          other storage types
   kolmogorov_512_general_f32                             non-slip s3 and s2b = s2 (general collision)
   kolmogorov_512_mrt_f32, kolmogorov_512_d3q19_{f32,f64,f16}   Appendix B and Appendix A
-  cavity_256_{cascaded,mrt}_f32                          lid-driven cavity, all walls
+  cavity_256_{cascaded,mrt}_f32, cavity_256_cascaded_f64   lid-driven cavity, all walls
   table_I_latency, table_I_bandwidth                     Table I's cascaded/SRT cost ratio
   taylor_green_128_{f64,f32}
   porous_640x320x320_f32, porous_640x320x320_general_f32
@@ -261,17 +261,17 @@ def v_kolmogorov_d3q19(storage):
     return run
 
 
-def v_cavity(collision):
+def v_cavity(collision, storage="f32"):
     def run(b: Bench):
         from paper_1801_04586_amd import Lattice
 
         cdims = (256, 256, 256)
         n = 256 ** 3
-        lat = Lattice(cdims, (1, 1, 1), "f32", b.workloads.rates(0.1 * 256 / 400.0), device=b.dev,
+        lat = Lattice(cdims, (1, 1, 1), storage, b.workloads.rates(0.1 * 256 / 400.0), device=b.dev,
                       collision=collision, wall_velocity={(1, 1): (0.1, 0.0, 0.0)})
         lat.init()
         lat.step(3)
-        bpn = bytes_per_node("f32", False, False)
+        bpn = bytes_per_node(storage, False, False)
         r = b.record(n, b.step_ms(lat), bpn, launch="two fused steps" if lat.uses_fused_pairs else "one step")
         if lat.uses_fused_pairs:
             lat.set_fused_steps(False)
@@ -557,6 +557,7 @@ VARIANTS = {
     "kolmogorov_512_d3q19_f16": v_kolmogorov_d3q19("f16"),
     "cavity_256_cascaded_f32": v_cavity("cascaded"),
     "cavity_256_mrt_f32": v_cavity("mrt"),
+    "cavity_256_cascaded_f64": v_cavity("cascaded", "f64"),
     "table_I_latency": v_table_I_latency,
     "table_I_bandwidth": v_table_I_bandwidth,
     "taylor_green_128_f64": v_taylor_green("f64"),

@@ -70,8 +70,8 @@ extern "C" {
  * Eq. (A1)-(A6): velocities without the eight corners, moments of Eq. (A2),
  * rates s3 for the six third-order and s4 for the three fourth-order moments;
  * s3b, s4b, s5 and s6 are unused).  D3Q19 has no adjoint (clbm_adjoint_step and
- * clbm_loss_seed return CLBM_EINVAL); with FP32 storage, and with FP64 storage
- * on periodic lattices, it takes fused step pairs like D3Q27 (see clbm_run). */
+ * clbm_loss_seed return CLBM_EINVAL); with FP32 or FP64 storage it takes fused
+ * step pairs like D3Q27 (see clbm_run). */
 typedef enum clbm_lattice {
     CLBM_D3Q27 = 0,
     CLBM_D3Q19 = 1
@@ -199,16 +199,14 @@ int clbm_step(clbm_ctx *ctx, const void *src, void *dst);
 
 /* nsteps steps from the state in a, using a and b as the two buffers; the
  * buffer that holds the final state is returned in *result (host, may be
- * NULL).  On lattices with FP32 storage (D3Q27 with the cascaded collision or
- * the MRT of Appendix B, D3Q19; any walls, moving or not, and solid nodes) and
- * on periodic lattices with FP64 storage (the same velocity sets and
- * collisions; no walls, no solid nodes), pairs of steps run as one fused
- * launch that keeps the intermediate state on chip (bitwise the same result as
- * two clbm_step calls) when the lattice fills the device: its 32 x 12 (x, y)
- * tile columns (32 x 16 for FP64 with the cascaded collision) times z chunks of
- * 8 planes give at least two blocks per compute unit (CLBM_OPT_* flags override
- * this); otherwise every step is one
- * clbm_step.  nsteps >= 0. */
+ * NULL).  On lattices with FP32 or FP64 storage (D3Q27 with the cascaded
+ * collision or the MRT of Appendix B, D3Q19; any walls, moving or not, and
+ * solid nodes), pairs of steps run as one fused launch that keeps the
+ * intermediate state on chip (bitwise the same result as two clbm_step calls)
+ * when the lattice fills the device: its 32 x 12 (x, y) tile columns (32 x 16
+ * for periodic FP64 lattices with the cascaded collision) times z chunks of 8
+ * planes give at least two blocks per compute unit (CLBM_OPT_* flags override
+ * this); otherwise every step is one clbm_step.  nsteps >= 0. */
 int clbm_run(clbm_ctx *ctx, void *a, void *b, int32_t nsteps, void **result);
 
 /* nsteps steps from the state in src, keeping every state (not in the paper; for the adjoint's

@@ -209,7 +209,8 @@ int collision_of(const clbm_ctx *c)
 // Rows of the fused kernel's tile on this lattice (D3Q19 takes the general cascaded collision).
 int fused_rows(const clbm_ctx *c)
 {
-    return t2_rows(c->d.storage == CLBM_F64, c->d.lattice == CLBM_D3Q19 ? kCascaded : collision_of(c));
+    return t2_rows(c->d.storage == CLBM_F64, c->d.lattice == CLBM_D3Q19 ? kCascaded : collision_of(c),
+                   c->links != nullptr);
 }
 
 int launch_step(clbm_ctx *c, const void *src, void *dst)
@@ -236,18 +237,16 @@ int launch_step(clbm_ctx *c, const void *src, void *dst)
     });
 }
 
-// Two fused steps per launch apply to lattices with FP32 storage (D3Q27 with the
-// cascaded collision or the MRT, D3Q19 with the cascaded collision), either
-// periodic or with a link table (solid nodes or walls, moving or not), and to
-// periodic lattices with FP64 storage (the same schemes; one block per compute
-// unit, whose LDS groups of doubles fill 103 KB, and no link-table variant).  For
-// 16-bit storage (half the bytes of FP32) the single-step kernel is faster, the
-// fused kernel's cost per step being set by its arithmetic and barriers rather
-// than by memory.
+// Two fused steps per launch apply to lattices with FP32 or FP64 storage (D3Q27
+// with the cascaded collision or the MRT, D3Q19 with the cascaded collision),
+// either periodic or with a link table (solid nodes or walls, moving or not); in
+// FP64 one block runs per compute unit, its LDS groups of doubles filling
+// 103-137 KB.  For 16-bit storage (half the bytes of FP32) the single-step kernel
+// is faster, the fused kernel's cost per step being set by its arithmetic and
+// barriers rather than by memory.
 bool fused_kind(const clbm_desc &d)
 {
-    const bool walls = d.wall[0] || d.wall[1] || d.wall[2];
-    return d.storage == CLBM_F32 || (d.storage == CLBM_F64 && !d.solid && !walls);
+    return d.storage == CLBM_F32 || d.storage == CLBM_F64;
 }
 
 // A lattice too small to give the fused kernel two blocks per compute unit (tile
@@ -278,7 +277,7 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         auto launch = [&](auto cc, auto qq) {
             constexpr int C = decltype(cc)::value;
             constexpr int Q = decltype(qq)::value;
-            using Tile = T2Tile<R, C>;
+            using Tile = T2Tile<R, C, SOLID>;
             T2Geom tg;
             tg.tiles_x = (c->geom.nx + kT2X - 1) / kT2X;
             tg.tiles_y = (c->geom.ny + Tile::Y - 1) / Tile::Y;
@@ -310,8 +309,10 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         if (coll == kMrt) return launch(std::integral_constant<int, kMrt>{}, Q27{});
         return launch(std::integral_constant<int, kCascaded>{}, Q27{});
     };
-    if (c->d.storage == CLBM_F64) {  // periodic lattices only (fused_kind)
-        if (c->links) return fail(c, CLBM_EINVAL, "fused FP64 pairs take no link table");
+    if (c->d.storage == CLBM_F64) {
+        if (c->links)
+            return c->d.force != nullptr ? go(double{}, std::true_type{}, std::true_type{})
+                                         : go(double{}, std::false_type{}, std::true_type{});
         return c->d.force != nullptr ? go(double{}, std::true_type{}, std::false_type{})
                                      : go(double{}, std::false_type{}, std::false_type{});
     }

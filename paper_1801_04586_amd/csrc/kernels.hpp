@@ -533,10 +533,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 }
 
 // ------------------------------------------------------------------ two fused steps (temporal blocking)
-// Two time steps per launch on FP32 lattices (and periodic FP64 lattices): D3Q27
-// with the cascaded collision or the MRT of Appendix B, and D3Q19 (Q = 19: only the
-// 19 population planes are read and written, the corner slots hold 0).  A block
-// owns a 32 x 12 tile of (x, y) columns (32 x 16 for FP64 with the cascaded
+// Two time steps per launch on FP32 and FP64 lattices: D3Q27 with the cascaded
+// collision or the MRT of Appendix B, and D3Q19 (Q = 19: only the 19 population
+// planes are read and written, the corner slots hold 0).  A block owns a 32 x 12
+// tile of (x, y) columns (32 x 16 for periodic FP64 lattices with the cascaded
 // collision, see t2_rows) and marches along a chunk of z planes.
 // For each plane it first runs step t -> t+1 on the tile plus a one-node halo
 // (34 x 14 nodes, pulling from HBM), keeping the results in LDS, and then step
@@ -562,7 +562,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const S *__restrict__ src, S *_
 // to 383 take the tile, wavefronts 6 and 7 the halo ring), whose registers hold the
 // node's e_z = +1 group and link word; the e_z = 0 group of plane z is in LDS,
 // and the e_z = -1 groups alternate between two LDS slots by plane parity so
-// that plane z's stays readable while plane z+1's is written (68.5 KB per block).
+// that plane z's stays readable while plane z+1's is written (68.5 KB per block in
+// FP32, 137 KB in FP64).
 // Population i's slot (inverse of pop_of_slot).
 __host__ __device__ constexpr int slot_of_pop(int i)
 {
@@ -621,11 +622,15 @@ constexpr int kT2X = 32, kT2HX = kT2X + 2;  // tile columns, and with the halo
 // 12 was fastest).  FP64: the ring of doubles leaves room for one block per CU, and 16 rows (10 waves,
 // 132 KB of LDS, at most 168 registers) ran the cascaded collision 7-16% faster than 12 rows, and 8
 // rows (two 6-wave blocks per CU) 5-15% slower; the MRT, whose FP64 update spills at 168
-// registers, keeps 12 rows and 256 registers (16 rows were 13% slower).
-__host__ __device__ constexpr int t2_rows(bool fp64, int coll) { return fp64 && coll != kMrt ? 16 : 12; }
-template <typename R, int COLL>
+// registers, keeps 12 rows and 256 registers (16 rows were 13% slower), and so does the link-table
+// variant, whose four LDS groups of doubles fill 137 KB at 12 rows.
+__host__ __device__ constexpr int t2_rows(bool fp64, int coll, bool links)
+{
+    return fp64 && coll != kMrt && !links ? 16 : 12;
+}
+template <typename R, int COLL, bool SOLID>
 struct T2Tile {
-    static constexpr int Y = t2_rows(sizeof(R) == 8, COLL);
+    static constexpr int Y = t2_rows(sizeof(R) == 8, COLL, SOLID);
     static constexpr int HY = Y + 2, H = kT2HX * HY;  // halo tile: 476 nodes at 12 rows, 612 at 16
     static constexpr int Block = (H + 63) / 64 * 64;  // 512 threads at 12 rows, 640 at 16
     // waves per SIMD the register budget must allow: 4 (128 registers) for FP32, 2 (256) for the
@@ -651,16 +656,15 @@ __device__ __forceinline__ uint32_t wrap_coord(int c, uint32_t n)
 // (the waves-per-EU bound sets the register budget: 128 for FP32 arithmetic; FP64 arithmetic,
 // whose values take two registers each, runs one block per CU with 168 or 256)
 template <typename S, bool FIELD, int COLL, bool SOLID, int Q = 27>
-__global__ __launch_bounds__((T2Tile<typename Traits<S>::R, COLL>::Block)) __attribute__((
-    amdgpu_waves_per_eu(T2Tile<typename Traits<S>::R, COLL>::WavesPerEU))) void k_step2(
+__global__ __launch_bounds__((T2Tile<typename Traits<S>::R, COLL, SOLID>::Block)) __attribute__((
+    amdgpu_waves_per_eu(T2Tile<typename Traits<S>::R, COLL, SOLID>::WavesPerEU))) void k_step2(
     const S *__restrict__ src, S *__restrict__ dst, Geom g, T2Geom tg, const uint32_t *__restrict__ links,
     const typename Traits<S>::R *__restrict__ field, Forcing<typename Traits<S>::R> fo,
     Rates<typename Traits<S>::R> rt)
 {
     using R = typename Traits<S>::R;
-    static_assert(!SOLID || std::is_same<R, float>::value, "the link-table variant is built for FP32 only");
-    static constexpr int kT2Y = T2Tile<R, COLL>::Y, kT2HY = T2Tile<R, COLL>::HY, kT2H = T2Tile<R, COLL>::H;
-    static constexpr int kT2Block = T2Tile<R, COLL>::Block;
+    using Tile = T2Tile<R, COLL, SOLID>;
+    static constexpr int kT2Y = Tile::Y, kT2HY = Tile::HY, kT2H = Tile::H, kT2Block = Tile::Block;
     // [0]: e_z = -1 group of plane z+1, [1]: e_z = 0 group of plane z, [2]: e_z = +1 group of plane z-1;
     // with SOLID, [0] and [3] hold the e_z = -1 groups of even and odd planes.  The ring holds the
     // arithmetic type, which represents every storable value exactly.
@@ -761,6 +765,7 @@ __global__ __launch_bounds__((T2Tile<typename Traits<S>::R, COLL>::Block)) __att
                         v[t] = R(0);
                     }
                 });
+                to_deviations<S, R, Q>(v);
             } else {
                 // the gather of Eq. (8) with its checks, planes in increasing order: a blocked
                 // link takes the node's own opposite population (plane ib), whose address is an
@@ -788,6 +793,7 @@ __global__ __launch_bounds__((T2Tile<typename Traits<S>::R, COLL>::Block)) __att
                     }
                     if constexpr (i < Q - 1) pl = next_plane(src, po, plane_bytes);
                 });
+                to_deviations<S, R, Q>(v);
             }
         } else {
             const S *__restrict__ pl = src;  // plane i, planes in increasing order
@@ -861,6 +867,7 @@ __global__ __launch_bounds__((T2Tile<typename Traits<S>::R, COLL>::Block)) __att
                 sfor<0, 27>([&](auto T) { v[decltype(T)::value] = R(0); });
             } else if (__all(lm == all_links<Q>())) {
                 sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = pull(TT); });
+                to_deviations<S, R, Q>(v);
             } else {
                 // a blocked link returns the node's own opposite population of step t+1 (Eq. (8)),
                 // plus the momentum of a moving wall as in gather()
@@ -888,6 +895,7 @@ __global__ __launch_bounds__((T2Tile<typename Traits<S>::R, COLL>::Block)) __att
                         if (mf && !open) v[t] += wall_term<t, Q, R>(nb, g);
                     }
                 });
+                to_deviations<S, R, Q>(v);
             }
         } else {
             sfor<0, 27>([&](auto TT) { v[decltype(TT)::value] = pull(TT); });
@@ -909,7 +917,10 @@ __global__ __launch_bounds__((T2Tile<typename Traits<S>::R, COLL>::Block)) __att
             uint64_t po = 0;
             sfor<0, Q>([&](auto II) {
                 constexpr int i = decltype(II)::value, t = slot_of_pop(i);
-                store_at(pl, nb_off, to_store<S>(v[t]));
+                if constexpr (Traits<S>::kDev)
+                    store_at(pl, nb_off, to_store<S>(v[t]));
+                else
+                    store_at(pl, nb_off, to_store<S>(v[t] + lattice_weight<Q, R>(t)));
                 if constexpr (i < Q - 1) pl = next_plane(dst, po, plane_bytes);
             });
         } else {

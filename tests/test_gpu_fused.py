@@ -1,6 +1,6 @@
-"""Fused two-step launches (clbm_run on FP32 D3Q27 lattices with the cascaded or the
-MRT collision, and on FP32 D3Q19 lattices: periodic, walled, moving walls, solid nodes; on periodic
-FP64 lattices of both schemes and collisions) are bitwise identical to single steps,
+"""Fused two-step launches (clbm_run on FP32 and FP64 D3Q27 lattices with the cascaded or the
+MRT collision, and on FP32 and FP64 D3Q19 lattices: periodic, walled, moving walls, solid nodes) are
+bitwise identical to single steps,
 across ragged tiles, thin lattices, odd step counts, both collision paths, with
 or without a force field, every wall combination, random solids and packed
 spheres; and they match the oracle."""
@@ -61,7 +61,7 @@ def test_fused_pairs_without_force_field(storage, rates):
     assert torch.equal(a, b)
 
 
-def test_fused_pairs_apply_to_fp32_lattices_and_periodic_fp64_lattices():
+def test_fused_pairs_apply_to_fp32_and_fp64_lattices():
     from paper_1801_04586_amd import Lattice
 
     dims = (8, 8, 8)
@@ -74,17 +74,18 @@ def test_fused_pairs_apply_to_fp32_lattices_and_periodic_fp64_lattices():
              ("f32", (0, 1, 0), None, None, "d3q27", "cascaded", True),
              ("f32", (0, 0, 0), sol, None, "d3q27", "cascaded", True),
              ("f32", (1, 1, 1), sol, None, "d3q27", "cascaded", True),
-             ("f64", (0, 1, 0), sol, None, "d3q27", "cascaded", False),
+             ("f64", (0, 1, 0), sol, None, "d3q27", "cascaded", True),
              ("f32", (0, 1, 0), sol, lid, "d3q27", "cascaded", True),
              ("f32", (1, 1, 1), None, lid, "d3q27", "cascaded", True),
              ("f32", (0, 1, 0), None, None, "d3q19", "cascaded", True),
              ("f32", (1, 1, 1), sol, lid, "d3q19", "cascaded", True),
-             ("f64", (0, 1, 0), None, None, "d3q19", "cascaded", False),
+             ("f64", (0, 1, 0), None, None, "d3q19", "cascaded", True),
              ("f64", (0, 0, 0), None, None, "d3q19", "cascaded", True),
-             ("f64", (0, 0, 0), sol, None, "d3q27", "cascaded", False),
+             ("f64", (0, 0, 0), sol, None, "d3q27", "cascaded", True),
+             ("f64", (1, 1, 1), sol, lid, "d3q19", "cascaded", True),
              ("f32", (0, 1, 0), None, None, "d3q27", "mrt", True),
              ("f32", (1, 1, 1), sol, lid, "d3q27", "mrt", True),
-             ("f64", (0, 1, 0), None, None, "d3q27", "mrt", False),
+             ("f64", (0, 1, 0), None, None, "d3q27", "mrt", True),
              ("f64", (0, 0, 0), None, None, "d3q27", "mrt", True)]
     for storage, walls, solid, wv, lattice, coll, fused in cases:
         lat = Lattice(dims, walls, storage, RATES, solid=solid, wall_velocity=wv, lattice=lattice, collision=coll)
@@ -132,10 +133,11 @@ def test_fused_pairs_by_default_only_on_lattices_that_fill_the_device():
         lat.close()
 
 
-def _run_solid(dims, walls, solid, steps, fused, f0, field, rates=RATES, wall_velocity=None, collision="cascaded"):
+def _run_solid(dims, walls, solid, steps, fused, f0, field, rates=RATES, wall_velocity=None, collision="cascaded",
+               storage="f32"):
     from paper_1801_04586_amd import Lattice
 
-    lat = Lattice(dims, walls, "f32", rates, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid,
+    lat = Lattice(dims, walls, storage, rates, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid,
                   wall_velocity=wall_velocity, collision=collision)
     lat.set_fused_steps(fused)
     assert lat.uses_fused_pairs == fused
@@ -157,14 +159,15 @@ def _start_walls(dims, walls, seed):
                                         ((5, 7, 2), (1, 0, 1)), ((96, 17, 1), (0, 1, 0)), ((1, 13, 9), (0, 1, 1)),
                                         ((40, 12, 3), (0, 0, 1))])
 @pytest.mark.parametrize("rates", [RATES, RATES_H1], ids=["general", "high1"])
-def test_fused_pairs_with_solids_are_bitwise_single_steps(dims, walls, rates):
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_fused_pairs_with_solids_are_bitwise_single_steps(dims, walls, rates, storage):
     g, f0 = _start_walls(dims, walls, 21)
     field = workloads.gaussian_force(dims, 1e-4, 22)
     solid = workloads.random_solids(dims, 0.2, 23)
     for steps in (2, 5):
-        a, _ = _run_solid(dims, walls, solid, steps, True, f0, field, rates)
-        b, _ = _run_solid(dims, walls, solid, steps, False, f0, field, rates)
-        assert torch.equal(a, b), (dims, walls, steps)
+        a, _ = _run_solid(dims, walls, solid, steps, True, f0, field, rates, storage=storage)
+        b, _ = _run_solid(dims, walls, solid, steps, False, f0, field, rates, storage=storage)
+        assert torch.equal(a, b), (dims, walls, steps, storage)
 
 
 def test_fused_pairs_with_packed_spheres_and_without_force_field():
@@ -189,13 +192,14 @@ def test_fused_pairs_with_walls_and_an_all_fluid_mask():
 
 @pytest.mark.parametrize("dims,walls", [((67, 19, 13), (0, 1, 0)), ((33, 9, 40), (1, 1, 1)), ((5, 7, 2), (1, 0, 1)),
                                         ((40, 12, 3), (0, 0, 1)), ((1, 13, 9), (0, 1, 1))])
-def test_fused_pairs_with_walls_only_are_bitwise_single_steps(dims, walls):
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_fused_pairs_with_walls_only_are_bitwise_single_steps(dims, walls, storage):
     g, f0 = _start_walls(dims, walls, 61)
     field = workloads.gaussian_force(dims, 1e-4, 62)
     for steps in (2, 5):
-        a, _ = _run_solid(dims, walls, None, steps, True, f0, field)
-        b, _ = _run_solid(dims, walls, None, steps, False, f0, field)
-        assert torch.equal(a, b), (dims, walls, steps)
+        a, _ = _run_solid(dims, walls, None, steps, True, f0, field, storage=storage)
+        b, _ = _run_solid(dims, walls, None, steps, False, f0, field, storage=storage)
+        assert torch.equal(a, b), (dims, walls, steps, storage)
 
 
 def _moving_faces(walls, seed):
@@ -205,24 +209,26 @@ def _moving_faces(walls, seed):
 
 @pytest.mark.parametrize("dims,walls,frac", [((38, 14, 9), (0, 1, 0), 0.0), ((35, 13, 11), (1, 1, 1), 0.0),
                                              ((35, 13, 11), (1, 1, 1), 0.15), ((20, 30, 7), (0, 1, 1), 0.1)])
-def test_fused_pairs_with_moving_walls_are_bitwise_single_steps(dims, walls, frac):
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_fused_pairs_with_moving_walls_are_bitwise_single_steps(dims, walls, frac, storage):
     """Every face of every walled axis moves, so edge and corner links cross two or three moving faces."""
     g, f0 = _start_walls(dims, walls, 71)
     solid = workloads.random_solids(dims, frac, 72) if frac else None
     wv = _moving_faces(walls, 73)
     for steps in (2, 3):
-        a, _ = _run_solid(dims, walls, solid, steps, True, f0, None, RATES_H1, wv)
-        b, _ = _run_solid(dims, walls, solid, steps, False, f0, None, RATES_H1, wv)
-        assert torch.equal(a, b), (dims, walls, frac, steps)
+        a, _ = _run_solid(dims, walls, solid, steps, True, f0, None, RATES_H1, wv, storage=storage)
+        b, _ = _run_solid(dims, walls, solid, steps, False, f0, None, RATES_H1, wv, storage=storage)
+        assert torch.equal(a, b), (dims, walls, frac, steps, storage)
 
 
-def test_fused_run_with_moving_walls_matches_oracle():
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-7), ("f64", 1e-14)])
+def test_fused_run_with_moving_walls_matches_oracle(storage, tol):
     dims, walls = (36, 15, 8), (1, 1, 1)
     g, f0 = _start_walls(dims, walls, 81)
     wv = _moving_faces(walls, 82)
     from paper_1801_04586_amd import Lattice
 
-    lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, -3e-6, 2e-6), wall_velocity=wv)
+    lat = Lattice(dims, walls, storage, RATES, force=(1e-5, -3e-6, 2e-6), wall_velocity=wv)
     lat.set_fused_steps(True)
     assert lat.uses_fused_pairs
     lat.set_populations(torch.from_numpy(f0))
@@ -230,18 +236,19 @@ def test_fused_run_with_moving_walls_matches_oracle():
     lat.step(4)
     got = lat.populations().cpu().numpy()
     ref = oracle.run(g, start, RATES, 4, force=(1e-5, -3e-6, 2e-6), wall_velocity=wv)
-    assert np.max(np.abs(got - ref)) < 1e-7
+    assert np.max(np.abs(got - ref)) < tol
     lat.close()
 
 
-def test_fused_run_with_solids_matches_oracle():
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-7), ("f64", 1e-14)])
+def test_fused_run_with_solids_matches_oracle(storage, tol):
     dims, walls = (37, 14, 9), (0, 1, 0)
     g, f0 = _start_walls(dims, walls, 51)
     field = workloads.gaussian_force(dims, 1e-4, 52)
     solid = workloads.random_solids(dims, 0.15, 53)
     from paper_1801_04586_amd import Lattice
 
-    lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid)
+    lat = Lattice(dims, walls, storage, RATES, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid)
     lat.set_fused_steps(True)
     assert lat.uses_fused_pairs
     lat.set_populations(torch.from_numpy(f0))
@@ -251,7 +258,7 @@ def test_fused_run_with_solids_matches_oracle():
     ref = oracle.run(g, start, RATES, 4, force=(1e-5, -3e-6, 2e-6), force_field=lat.force_field.double().cpu().numpy(),
                      solid=solid)
     fl = solid == 0
-    assert np.max(np.abs(got[:, fl] - ref[:, fl])) < 1e-7
+    assert np.max(np.abs(got[:, fl] - ref[:, fl])) < tol
     lat.close()
 
 
@@ -388,7 +395,8 @@ def test_trajectory_refuses_shared_buffers():
                                                     ((40, 12, 3), (0, 1, 1), 0.0, False),
                                                     ((35, 13, 11), (1, 1, 1), 0.15, True),
                                                     ((38, 14, 9), (0, 1, 0), 0.0, True)])
-def test_fused_mrt_pairs_are_bitwise_single_steps(dims, walls, frac, moving):
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_fused_mrt_pairs_are_bitwise_single_steps(dims, walls, frac, moving, storage):
     """The raw-moment MRT of Appendix B in fused pairs: periodic with a force field, walls, solids and
     moving faces, against single MRT steps."""
     g, f0 = _start_walls(dims, walls, 81)
@@ -396,15 +404,15 @@ def test_fused_mrt_pairs_are_bitwise_single_steps(dims, walls, frac, moving):
     solid = workloads.random_solids(dims, frac, 83) if frac else None
     wv = _moving_faces(walls, 84) if moving else None
     for steps in (2, 5):
-        a, _ = _run_solid(dims, walls, solid, steps, True, f0, field, RATES, wv, "mrt")
-        b, _ = _run_solid(dims, walls, solid, steps, False, f0, field, RATES, wv, "mrt")
-        assert torch.equal(a, b), (dims, walls, frac, moving, steps)
+        a, _ = _run_solid(dims, walls, solid, steps, True, f0, field, RATES, wv, "mrt", storage)
+        b, _ = _run_solid(dims, walls, solid, steps, False, f0, field, RATES, wv, "mrt", storage)
+        assert torch.equal(a, b), (dims, walls, frac, moving, steps, storage)
 
 
-def _run_q19(dims, walls, solid, steps, fused, f0, field, wall_velocity=None):
+def _run_q19(dims, walls, solid, steps, fused, f0, field, wall_velocity=None, storage="f32"):
     from paper_1801_04586_amd import Lattice
 
-    lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid,
+    lat = Lattice(dims, walls, storage, RATES, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid,
                   wall_velocity=wall_velocity, lattice="d3q19")
     lat.set_fused_steps(fused)
     assert lat.uses_fused_pairs == fused
@@ -423,7 +431,8 @@ def _run_q19(dims, walls, solid, steps, fused, f0, field, wall_velocity=None):
                                                     ((5, 7, 2), (1, 0, 1), 0.1, False),
                                                     ((35, 13, 11), (1, 1, 1), 0.15, True),
                                                     ((38, 14, 9), (0, 1, 0), 0.0, True)])
-def test_fused_d3q19_pairs_are_bitwise_single_steps(dims, walls, frac, moving):
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_fused_d3q19_pairs_are_bitwise_single_steps(dims, walls, frac, moving, storage):
     """The D3Q19 scheme of Appendix A in fused pairs (19 planes; the corner slots hold no population),
     periodic with a force field, with walls, solids and moving faces, against single D3Q19 steps."""
     g = oracle.Geometry(dims, walls)
@@ -433,19 +442,20 @@ def test_fused_d3q19_pairs_are_bitwise_single_steps(dims, walls, frac, moving):
     solid = workloads.random_solids(dims, frac, 94) if frac else None
     wv = _moving_faces(walls, 95) if moving else None
     for steps in (2, 5):
-        a, _ = _run_q19(dims, walls, solid, steps, True, f0, field, wv)
-        b, _ = _run_q19(dims, walls, solid, steps, False, f0, field, wv)
-        assert torch.equal(a, b), (dims, walls, frac, moving, steps)
+        a, _ = _run_q19(dims, walls, solid, steps, True, f0, field, wv, storage)
+        b, _ = _run_q19(dims, walls, solid, steps, False, f0, field, wv, storage)
+        assert torch.equal(a, b), (dims, walls, frac, moving, steps, storage)
 
 
-def test_fused_d3q19_pairs_match_the_oracle():
+@pytest.mark.parametrize("storage,tol", [("f32", 5e-8), ("f64", 1e-14)])
+def test_fused_d3q19_pairs_match_the_oracle(storage, tol):
     dims, walls = (37, 15, 10), (0, 1, 1)
     g = oracle.Geometry(dims, walls)
     rho0, u0 = workloads.random_state_fields(dims, 96, du=0.05, drho=0.02)
     f0 = oracle.init(g, rho0, u0, lattice="d3q19") + workloads.random_populations_perturbation(dims, 97, 1e-3)[:19]
     field = workloads.gaussian_force(dims, 1e-4, 98)
     solid = workloads.random_solids(dims, 0.1, 99)
-    _, got = _run_q19(dims, walls, solid, 4, True, f0, field)
+    _, got = _run_q19(dims, walls, solid, 4, True, f0, field, storage=storage)
     ref = oracle.run(g, f0, RATES, 4, force=(1e-5, -3e-6, 2e-6), force_field=field, solid=solid, lattice="d3q19")
     fl = solid == 0
-    assert np.max(np.abs(got[:, fl] - ref[:, fl])) < 5e-8
+    assert np.max(np.abs(got[:, fl] - ref[:, fl])) < tol
