@@ -27,11 +27,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _lattice(dims, walls, storage, rates, force=(0.0, 0.0, 0.0), field=None, solid=None, lattice="d3q27",
-             collision="cascaded"):
+             collision="cascaded", wall_velocity=None):
     from paper_1801_04586_amd import Lattice
 
     return Lattice(dims, walls, storage, rates, force=force, force_field=field, solid=solid, lattice=lattice,
-                   collision=collision)
+                   collision=collision, wall_velocity=wall_velocity)
 
 
 def _window(dims, walls, c, k):
@@ -52,7 +52,7 @@ def _window(dims, walls, c, k):
 
 
 def _cone_parity(lat, dims, walls, rates, k, samples, rho0=None, u0=None, force=(0, 0, 0), field=None, solid=None,
-                 lattice="d3q27", model="cascaded"):
+                 lattice="d3q27", model="cascaded", wall_velocity=None):
     """Max |f_gpu - f_oracle| over the sampled nodes after k steps from f_eq(rho0, u0)."""
     got = lat.sample(samples)
     err = 0.0
@@ -63,7 +63,7 @@ def _cone_parity(lat, dims, walls, rates, k, samples, rho0=None, u0=None, force=
         g = oracle.Geometry(dims, walls, o, w)
         f = oracle.init(g, sub(rho0), sub(u0), lattice=lattice, model=model)
         f = oracle.run(g, f, rates, k, force=force, force_field=sub(field), solid=sub(solid), lattice=lattice,
-                       model=model)
+                       model=model, wall_velocity=wall_velocity)
         ref = f[:, c[2] - o[2], c[1] - o[1], c[0] - o[0]]  # the node sits at offset c - origin
         if solid is not None and solid[c[2], c[1], c[0]]:
             continue
@@ -303,6 +303,33 @@ def test_kolmogorov_512_storage_errors_against_fp64_after_500_steps(kolmogorov_i
         torch.cuda.empty_cache()
 
 
+# ----------------------------------------------------------------------------- lid-driven cavity 256^3
+@pytest.mark.parametrize("storage,collision,tol", [("f32", "cascaded", 2e-8), ("f32", "mrt", 2e-8),
+                                                   ("f64", "cascaded", 5e-15)])
+def test_cavity_256_sampled_parity_fused(storage, collision, tol):
+    """The benchmark's lid-driven cavity (256^3, walls on every axis, the face y = 255 moving along x
+    with U = 0.1) at its full size and launch configuration (one fused pair of the link-table kernel and
+    one single step), from a random velocity field, against the oracle on the light cones of corner,
+    edge, lid and interior nodes."""
+    dims, walls = (256, 256, 256), (1, 1, 1)
+    wv = {(1, 1): (0.1, 0.0, 0.0)}
+    rates = workloads.rates(0.1 * 256 / 400.0)
+    u0 = workloads.uniform_random_velocity(dims, 1e-3, 79)
+    k = 3
+    lat = _lattice(dims, walls, storage, rates, collision=collision, wall_velocity=wv)
+    assert lat.uses_fused_pairs
+    lat.init(None, u0)
+    lat.step(k)
+    samples = [(0, 0, 0), (255, 255, 255), (0, 255, 0), (255, 255, 0), (128, 255, 128), (17, 254, 200),
+               (255, 0, 128), (100, 100, 100), (3, 255, 250), (128, 0, 255), (1, 253, 2)]
+    err = _cone_parity(lat, dims, walls, rates, k, samples, None, u0, model=collision, wall_velocity=wv)
+    print(f"cavity 256^3 {storage} {collision}, fused pair + one step: max |f - f_oracle| {err:.2e}")
+    assert err < tol, err
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------------------- porous duct 640x320x320
 @pytest.fixture(scope="module")
 def porous_mask():
@@ -311,12 +338,17 @@ def porous_mask():
     return mask
 
 
-def test_porous_duct_sampled_parity_next_to_solids(porous_mask):
+@pytest.mark.parametrize("storage,tol", [("f32", 5e-9), ("f64", 5e-15)])
+def test_porous_duct_sampled_parity_next_to_solids(storage, tol, porous_mask):
+    """The porous duct at its full size in the benchmark's launch configuration (one fused pair of the
+    link-table kernel and one single step), FP32 and FP64 storage, against the oracle on the light
+    cones of fluid nodes next to solids and of nodes at the walls and corners."""
     cfg = workloads.POROUS
     dims, walls = cfg.dims, cfg.walls
     u0 = workloads.uniform_random_velocity(dims, 1e-3, 77)
     k = 3
-    lat = _lattice(dims, walls, "f32", cfg.rates(), force=cfg.force_uniform, solid=porous_mask)
+    lat = _lattice(dims, walls, storage, cfg.rates(), force=cfg.force_uniform, solid=porous_mask)
+    assert lat.uses_fused_pairs
     lat.init(None, u0)
     lat.step(k)
     # fluid nodes with a solid neighbour, plus nodes at the walls and corners
@@ -334,8 +366,11 @@ def test_porous_duct_sampled_parity_next_to_solids(porous_mask):
     samples = [s for s in samples if porous_mask[s[2], s[1], s[0]] == 0]
     err = _cone_parity(lat, dims, walls, cfg.rates(), k, samples, None, u0, force=cfg.force_uniform,
                        solid=porous_mask)
-    assert err < 5e-9, err
+    print(f"porous duct {storage}, fused pair + one step: max |f - f_oracle| {err:.2e}")
+    assert err < tol, err
     lat.close()
+    del lat
+    torch.cuda.empty_cache()
 
 
 def test_porous_duct_mass_conservation_and_flow(porous_mask):
