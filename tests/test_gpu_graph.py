@@ -17,16 +17,17 @@ pytestmark = pytest.mark.gpu
 RATES = np.array([1.0, 1.0, 1.6, 1.2, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
 
 
-def _lattice(dims, walls, solid, field):
+def _lattice(dims, walls, solid, field, storage):
     from paper_1801_04586_amd import Lattice
 
-    lat = Lattice(dims, walls, "f32", RATES, force=(1e-5, 0.0, 0.0), force_field=field, solid=solid)
+    lat = Lattice(dims, walls, storage, RATES, force=(1e-5, 0.0, 0.0), force_field=field, solid=solid)
     lat.set_fused_steps(True)
     return lat
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64"])
 @pytest.mark.parametrize("walls,frac", [((0, 0, 0), 0.0), ((0, 1, 1), 0.1)], ids=["periodic", "walls_solids"])
-def test_captured_run_replays_bitwise_like_eager_steps(walls, frac):
+def test_captured_run_replays_bitwise_like_eager_steps(walls, frac, storage):
     dims = (70, 30, 24)
     g = oracle.Geometry(dims, walls)
     rho0, u0 = workloads.random_state_fields(dims, 91, du=0.05, drho=0.02)
@@ -35,7 +36,7 @@ def test_captured_run_replays_bitwise_like_eager_steps(walls, frac):
     solid = workloads.random_solids(dims, frac, 94) if frac else None
 
     # eager reference: three rounds of 8 steps (four fused launches each)
-    ref = _lattice(dims, walls, solid, field)
+    ref = _lattice(dims, walls, solid, field, storage)
     assert ref.uses_fused_pairs
     ref.set_populations(torch.from_numpy(f0))
     expected = []
@@ -44,7 +45,7 @@ def test_captured_run_replays_bitwise_like_eager_steps(walls, frac):
         expected.append(ref.state.clone())
     ref.close()
 
-    lat = _lattice(dims, walls, solid, field)
+    lat = _lattice(dims, walls, solid, field, storage)
     lat.set_populations(torch.from_numpy(f0))
     start = lat.state.clone()
     lat.step(2)  # first launches outside the capture (the context sizes its fused launches once)

@@ -283,16 +283,16 @@ def test_runs_are_bitwise_deterministic():
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_step_parity_with_a_force_scale_and_fused_pairs(storage):
     """clbm_set_force with a scale other than 1 (time-dependent forcing): the kernels use
-    F = uniform + scale * field; the oracle is given the scaled field.  FP32 runs fused pairs too."""
+    F = uniform + scale * field; the oracle is given the scaled field.  Both storage types run fused
+    pairs (the link-table variant: the duct has walls)."""
     dims, walls = (37, 13, 16), (0, 1, 0)
     g, f0 = _random_start(dims, walls, 91)
     field = workloads.gaussian_force(dims, 1e-4, 92)
     force, scale = (2e-5, -1e-5, 3e-6), -3.25
     lat = _lattice(dims, walls, storage, force=force, field=field)
     lat.set_force(force, field, scale)
-    if storage == "f32":
-        lat.set_fused_steps(True)
-        assert lat.uses_fused_pairs
+    lat.set_fused_steps(True)
+    assert lat.uses_fused_pairs
     lat.set_populations(torch.from_numpy(f0))
     start = lat.populations().cpu().numpy()
     Fs = scale * lat.force_field.double().cpu().numpy()
