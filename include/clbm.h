@@ -163,8 +163,9 @@ const char *clbm_last_error(const clbm_ctx *ctx);
  * NULL.  Allocates device scratch for reductions (130 KiB; on D3Q27 cascaded
  * lattices, whose adjoint keeps one row of partial sums per 256 nodes, 0.26
  * bytes per node if that is more) and, when
- * desc->solid is given or the lattice has walls and takes fused step pairs
- * (see clbm_run), a link table of 4 bytes per node built from the solid mask
+ * desc->solid is given or the lattice has walls and FP32 or FP64 storage (the
+ * storage types with fused step pairs, see clbm_run), a link table of 4 bytes
+ * per node built from the solid mask
  * and the walls by a kernel enqueued on `stream` (the mask must be ready when
  * that kernel runs; it is not referenced afterwards).  *out is set to NULL on
  * error. */
