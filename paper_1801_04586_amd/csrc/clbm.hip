@@ -316,6 +316,7 @@ int launch_step2(clbm_ctx *c, const void *src, void *dst)
         return c->d.force != nullptr ? go(double{}, std::true_type{}, std::false_type{})
                                      : go(double{}, std::false_type{}, std::false_type{});
     }
+    if (c->d.storage != CLBM_F32) return fail(c, CLBM_EINVAL, "fused step pairs take FP32 or FP64 storage");
     if (c->links)
         return c->d.force != nullptr ? go(float{}, std::true_type{}, std::true_type{})
                                      : go(float{}, std::false_type{}, std::true_type{});
