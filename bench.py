@@ -24,6 +24,7 @@ those (one lattice per process, for profilers):
   porous_640x320x320_f32, porous_640x320x320_general_f32
   adjoint_channel_64_f32                                 end-to-end gradient, T = 200, K = 20
   adjoint_porous_256x128x128_f32                         adjoint step, recompute, backward, gradient
+  adjoint_porous_256x128x128_f64                         adjoint step, recompute, backward (FP64 storage)
   adjoint_porous_640x320x320_f32                         adjoint step and recompute on the full duct
 plus the velocity error of every storage type against FP64 after 500 steps,
 and the FP64 CPU oracle on bounded samples.
@@ -53,6 +54,7 @@ HEADLINE = "kolmogorov_512_f32"
 # 2 x 3 x 4, force field 3 x 4, solid mask 1; counted over all nodes (the kernel reads and writes whole
 # lines, solid nodes included), as "frac"; "frac_fluid" counts fluid nodes only
 ADJ_BYTES = 27 * 4 * 3 + 24 + 12 + 1
+ADJ_BYTES_F64 = 27 * 8 * 3 + 48 + 24 + 1  # FP64 storage: state, lambda in and out, dJ/dF rmw, force, mask
 
 
 def log(*a):
@@ -435,13 +437,13 @@ def v_adjoint_channel(b: Bench):
             "note": "forward T steps + recompute T steps + T adjoint steps, 64^3 (cache-resident, launch-bound)"}
 
 
-def _adjoint_lattice(b: Bench, adims):
+def _adjoint_lattice(b: Bench, adims, storage="f32"):
     from paper_1801_04586_amd import Lattice
 
     wl = b.workloads
     mask = porous_mask(b, adims)
     Fa = wl.gaussian_force(adims, 1e-6, wl.SEED)
-    lat = Lattice(adims, (0, 1, 1), "f32", wl.rates(0.02), force=(2e-6, 0, 0), force_field=Fa, solid=mask,
+    lat = Lattice(adims, (0, 1, 1), storage, wl.rates(0.02), force=(2e-6, 0, 0), force_field=Fa, solid=mask,
                   device=b.dev)
     lat.init()
     lat.step(5)
@@ -454,10 +456,11 @@ def _adjoint_step_and_recompute(b: Bench, lat, K: int, keep: int):
     plus K adjoint steps)."""
     torch = b.torch
     shape = lat.shape
-    ut = torch.zeros((3,) + shape, dtype=torch.float32, device=b.dev)
-    lam = torch.empty((27,) + shape, dtype=torch.float32, device=b.dev)
+    dt = lat.ctx.adjoint_dtype  # FP64 for FP64 storage, else FP32
+    ut = torch.zeros((3,) + shape, dtype=dt, device=b.dev)
+    lam = torch.empty((27,) + shape, dtype=dt, device=b.dev)
     lam2 = torch.empty_like(lam)
-    gF = torch.zeros((3,) + shape, dtype=torch.float32, device=b.dev)
+    gF = torch.zeros((3,) + shape, dtype=dt, device=b.dev)
     gs = torch.zeros(10, dtype=torch.float64, device=b.dev)
     lat.ctx.loss_seed(lat.state, ut, lam, gF, None)
     bufs = [lam, lam2]
@@ -485,6 +488,25 @@ def _adjoint_step_and_recompute(b: Bench, lat, K: int, keep: int):
         seg_ms = b.ms(segment, 1, reps=5)
     del states
     return adj_ms, traj_ms, seg_ms
+
+
+def v_adjoint_porous_crop_f64(b: Bench):
+    """The adjoint step, its recompute and one backward segment (K = 20) on the same 256x128x128 crop with
+    FP64 storage (FP64 adjoint populations and force gradient)."""
+    np = b.np
+    adims, K = (256, 128, 128), 20
+    lat, mask, _ = _adjoint_lattice(b, adims, "f64")
+    an = int(np.prod(adims))
+    adj_ms, traj_ms, seg_ms = _adjoint_step_and_recompute(b, lat, K, K - 1)
+    fl = float((mask == 0).mean())
+    r = {"adjoint": b.record(an, adj_ms, ADJ_BYTES_F64,
+                             frac_fluid=round(fl * ADJ_BYTES_F64 * an / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
+         "recompute": b.record(an, traj_ms, bytes_per_node("f64", True, True), launch="clbm_trajectory (single steps)"),
+         "backward_segment_K20": {"ms": round(seg_ms, 4), "adjoint_steps_per_s_M": round(an * K / (seg_ms * 1e-3) / 1e6, 1),
+                                  "note": "recompute of 19 states + 20 adjoint steps, as the gradient runs it"},
+         "solid_fraction": round(float(mask.mean()), 4)}
+    b.done(lat)
+    return r
 
 
 def v_adjoint_porous_crop(b: Bench):
@@ -566,6 +588,7 @@ VARIANTS = {
     "porous_640x320x320_general_f32": v_porous(True),
     "adjoint_channel_64_f32": v_adjoint_channel,
     "adjoint_porous_256x128x128_f32": v_adjoint_porous_crop,
+    "adjoint_porous_256x128x128_f64": v_adjoint_porous_crop_f64,
     "adjoint_porous_640x320x320_f32": v_adjoint_porous_full,
 }
 

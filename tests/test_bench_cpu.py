@@ -32,8 +32,9 @@ def test_algorithmic_bytes_per_node_update(storage, field, solid, q, expected):
 
 def test_adjoint_bytes_per_node():
     """State 27 x 4 read, lambda 27 x 4 read and written, dJ/dF 3 x 4 read and written, force field
-    3 x 4 read, mask 1 byte."""
+    3 x 4 read, mask 1 byte; with FP64 storage every one of these but the mask in 8-byte words."""
     assert bench.ADJ_BYTES == 108 + 216 + 24 + 12 + 1 == 361
+    assert bench.ADJ_BYTES_F64 == 216 + 432 + 48 + 24 + 1 == 721
 
 
 def test_more_than_one_gpu_is_refused():
